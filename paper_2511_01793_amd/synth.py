@@ -1,0 +1,210 @@
+"""Seeded synthetic ptychography workloads (inputs only).
+
+This module builds the inputs that both the HIP path and the FP64 oracle
+consume: a ground-truth object and probe, scan positions, and the measured
+far-field intensities of the simulated experiment.  It holds none of the
+reconstruction method's arithmetic (no revised exit wave, no surrogate step,
+no multigrid); the only transform it applies is the forward model that
+produces the data, d_k = |F(Q* . P_k z*)|^2 (+ Poisson noise), of Sec. 2.1.
+
+Recipe (the paper's Baboon/Cameraman images, zone-plate probe and beamline
+data are not available; these seeded stand-ins take their place):
+
+* object: two independent sums of 20 Gaussian blobs (centre ~ U[0, n)^2,
+  width ~ U[n/40, n/10], weight ~ U[-1, 1]), each min-max normalised to
+  [0, 1]; |z*| = 0.8 + 0.2 f_A, arg z* = pi (f_phi - 1/2);
+* true probe: Gaussian of width sigma (6 px for m = 32, 0.1875 m otherwise)
+  times a quadratic defocus phase exp(i rho^2 / sigma^2), centred on the
+  window centre ((m-1)/2, (m-1)/2);
+* initial probe: a broader (1.5 sigma) zero-phase Gaussian, later scaled by
+  the dp_avg rule of Sec. 4.1; initial object z = 1 (Sec. 4.1);
+* positions: jittered raster or Fermat spiral, integer top-left corners
+  clamped to [0, n - m];
+* intensities: computed in float64, stored as float32, unshifted (DC at
+  [0, 0]); Poisson configurations first scale the true probe so that the
+  mean photon count per pattern equals the target, then draw counts.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "Problem",
+    "make_object",
+    "true_probe",
+    "initial_probe",
+    "raster_positions",
+    "fermat_positions",
+    "simulate_intensities",
+    "make_problem",
+    "CONFIGS",
+]
+
+
+def make_object(n: int, rng: np.random.Generator, n_blobs: int = 20) -> np.ndarray:
+    """Smooth complex test object, amplitude in [0.8, 1] and phase in [-pi/2, pi/2]."""
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+
+    def blob_sum() -> np.ndarray:
+        f = np.zeros((n, n))
+        for _ in range(n_blobs):
+            cy, cx = rng.uniform(0, n, size=2)
+            s = rng.uniform(n / 40.0, n / 10.0)
+            w = rng.uniform(-1.0, 1.0)
+            f += w * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2.0 * s * s))
+        f -= f.min()
+        mx = f.max()
+        return f / mx if mx > 0 else f
+
+    fa = blob_sum()
+    fp = blob_sum()
+    return (0.8 + 0.2 * fa) * np.exp(1j * np.pi * (fp - 0.5))
+
+
+def probe_sigma(m: int) -> float:
+    return 6.0 if m == 32 else 0.1875 * m
+
+
+def true_probe(m: int, sigma: float | None = None) -> np.ndarray:
+    """Defocused Gaussian probe (float64 complex)."""
+    s = probe_sigma(m) if sigma is None else sigma
+    c = (m - 1) / 2.0
+    yy, xx = np.mgrid[0:m, 0:m].astype(np.float64)
+    rho2 = (yy - c) ** 2 + (xx - c) ** 2
+    return np.exp(-rho2 / (2.0 * s * s)) * np.exp(1j * rho2 / (s * s))
+
+
+def initial_probe(m: int, sigma: float | None = None) -> np.ndarray:
+    """Broader zero-phase Gaussian guess (before the dp_avg scaling)."""
+    s = 1.5 * (probe_sigma(m) if sigma is None else sigma)
+    c = (m - 1) / 2.0
+    yy, xx = np.mgrid[0:m, 0:m].astype(np.float64)
+    return np.exp(-((yy - c) ** 2 + (xx - c) ** 2) / (2.0 * s * s)).astype(np.complex128)
+
+
+def raster_positions(n: int, m: int, side: int, step: int, jitter: int,
+                     rng: np.random.Generator) -> np.ndarray:
+    """side x side raster, integer jitter in {-J..J}, clamped to [0, n-m]."""
+    off = (n - m - (side - 1) * step) // 2
+    pos = np.empty((side * side, 2), dtype=np.int64)
+    k = 0
+    for i in range(side):
+        for j in range(side):
+            pos[k] = (off + i * step, off + j * step)
+            k += 1
+    if jitter > 0:
+        pos += rng.integers(-jitter, jitter + 1, size=pos.shape)
+    return np.clip(pos, 0, n - m).astype(np.int32)
+
+
+def fermat_positions(n: int, m: int, count: int) -> np.ndarray:
+    """Fermat spiral r_i = c sqrt(i), theta_i = i * 137.5078 deg, centred."""
+    c = ((n - m) / 2.0 - 1.0) / math.sqrt(count)
+    i = np.arange(count, dtype=np.float64)
+    r = c * np.sqrt(i)
+    th = np.deg2rad(137.5078) * i
+    ctr = (n - m) / 2.0
+    pos = np.stack([np.rint(ctr + r * np.sin(th)), np.rint(ctr + r * np.cos(th))], axis=1)
+    return np.clip(pos, 0, n - m).astype(np.int32)
+
+
+def simulate_intensities(probe: np.ndarray, obj: np.ndarray, positions: np.ndarray,
+                         chunk: int = 512) -> np.ndarray:
+    """Noiseless far-field intensities |F(Q . P_k z)|^2 in float64 (forward model, Sec. 2.1)."""
+    m = probe.shape[0]
+    out = np.empty((positions.shape[0], m, m), dtype=np.float64)
+    for s in range(0, positions.shape[0], chunk):
+        p = positions[s:s + chunk]
+        stack = np.stack([obj[r:r + m, c:c + m] for r, c in p]) * probe
+        out[s:s + chunk] = np.abs(np.fft.fft2(stack)) ** 2
+    return out
+
+
+@dataclasses.dataclass
+class Problem:
+    """One synthetic reconstruction problem; arrays in the dtypes both paths consume."""
+    name: str
+    n: int
+    m: int
+    positions: np.ndarray        # (N, 2) int32 (row, col) top-left
+    intensities: np.ndarray      # (N, m, m) float32, unshifted
+    probe_true: np.ndarray       # (m, m) complex128 (photon-scaled)
+    object_true: np.ndarray      # (n, n) complex128
+    probe_init: np.ndarray       # (m, m) complex64, NOT yet dp_avg-normalised
+    object_init: np.ndarray      # (n, n) complex64, all ones
+    minibatch: int
+    levels: int
+    alpha: float
+    alpha_z: float
+    epochs: int
+    seed: int
+    photons: float | None
+    noiseless: np.ndarray | None = None   # float64 noiseless intensities (small configs only)
+
+    @property
+    def n_pos(self) -> int:
+        return int(self.positions.shape[0])
+
+
+# name -> generator parameters (see module docstring)
+CONFIGS = {
+    # plain single level: 128^2 object, 32^2 probe, 10x10 raster step 8 jitter 1, noiseless
+    "c1": dict(n=128, m=32, scan=("raster", 10, 8, 1), photons=None, B=10, L=1, alpha=0.01, epochs=50, idx=1),
+    # two-level multigrid: 512^2 object, 64^2 probe, 40x40 raster step 10 jitter 2, 1e6 photons
+    "c2": dict(n=512, m=64, scan=("raster", 40, 10, 2), photons=1e6, B=64, L=2, alpha=0.05, epochs=100, idx=2),
+    # batching: 1024^2 object, 128^2 probe, Fermat spiral of 10000, 1e7 photons, 3 levels
+    "c3": dict(n=1024, m=128, scan=("fermat", 10000), photons=1e7, B=256, L=3, alpha=0.05, epochs=20, idx=3),
+    # differentiation: 256^2 object, 64^2 probe, 20x20 raster step 10, noiseless
+    "c4": dict(n=256, m=64, scan=("raster", 20, 10, 0), photons=None, B=400, L=1, alpha=0.05, epochs=0, idx=4),
+}
+
+
+def make_problem(name: str, *, n: int | None = None, m: int | None = None, scan=None,
+                 photons: float | None | str = "cfg", B: int | None = None, L: int | None = None,
+                 alpha: float | None = None, seed: int | None = None,
+                 keep_noiseless: bool = False) -> Problem:
+    """Build a named configuration (optionally overriding its parameters)."""
+    cfg = dict(CONFIGS[name]) if name in CONFIGS else dict(
+        n=64, m=16, scan=("raster", 4, 12, 1), photons=None, B=4, L=1, alpha=0.05, epochs=10, idx=9)
+    n = cfg["n"] if n is None else n
+    m = cfg["m"] if m is None else m
+    scan = cfg["scan"] if scan is None else scan
+    photons = cfg["photons"] if photons == "cfg" else photons
+    B = cfg["B"] if B is None else B
+    L = cfg["L"] if L is None else L
+    alpha = cfg["alpha"] if alpha is None else alpha
+    seed = 1000 + cfg["idx"] if seed is None else seed
+    rng = np.random.default_rng(seed)
+
+    obj = make_object(n, rng)
+    probe = true_probe(m)
+    if scan[0] == "raster":
+        pos = raster_positions(n, m, scan[1], scan[2], scan[3], rng)
+    else:
+        pos = fermat_positions(n, m, scan[1])
+    d = simulate_intensities(probe, obj, pos)
+    if photons is not None:
+        scale = photons / d.sum(axis=(1, 2)).mean()
+        probe = probe * math.sqrt(scale)
+        d = d * scale
+        meas = rng.poisson(d).astype(np.float32)
+    else:
+        meas = d.astype(np.float32)
+    return Problem(
+        name=name, n=n, m=m, positions=pos, intensities=meas,
+        probe_true=probe, object_true=obj,
+        probe_init=initial_probe(m).astype(np.complex64),
+        object_init=np.ones((n, n), dtype=np.complex64),
+        minibatch=B, levels=L, alpha=alpha, alpha_z=1.0,
+        epochs=cfg["epochs"], seed=seed, photons=photons,
+        noiseless=d if keep_noiseless else None,
+    )
+
+
+def noise_percent(noisy: np.ndarray, clean: np.ndarray) -> float:
+    """Noise% (amplitude) of Sec. 4.1: 100 sqrt(sum ||d - d~||^2 / sum ||d~||^2)."""
+    diff = noisy.astype(np.float64) - clean
+    return 100.0 * math.sqrt(float((diff * diff).sum()) / float((clean * clean).sum()))
