@@ -1,0 +1,194 @@
+/*
+ * libemagpie — MI355X (gfx950) implementation of the eMAGPIE stochastic
+ * surrogate-minimisation epoch for blind ptychographic phase retrieval
+ * (Zhang, Deng, Jiang, Di, "Stochastic Multigrid Method for Blind
+ * Ptychographic Phase Retrieval", arXiv 2511.01793).
+ *
+ * Problem statement (Sec. 2.1): recover a complex object z (n x n) and a
+ * complex probe Q (m x m) from far-field intensities d_k = |F(Q . P_k z)|^2
+ * measured at N scan positions, where P_k selects the m x m window whose
+ * top-left corner is positions[k] and F is the unnormalised 2-D DFT.
+ *
+ * Conventions shared by every entry point:
+ *  - All arrays are row-major.  Complex arrays are interleaved {re, im}
+ *    pairs: float pairs (complex64) everywhere except the float64 gradient,
+ *    which takes double pairs (complex128).
+ *  - Pointers named *_dev are device (HBM) pointers; *_host are host
+ *    pointers.  The caller owns every buffer it passes; the library never
+ *    allocates device memory: its scratch lives in the caller's workspace.
+ *  - `stream` is a hipStream_t passed as void*; all device work is
+ *    enqueued on it and is asynchronous unless stated otherwise.
+ *  - Every call returns an emagpie_status; argument errors are detected on
+ *    the host before anything is enqueued and leave all buffers untouched.
+ *    emagpie_last_error() returns a message for the last failure on the
+ *    calling thread.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Results are deterministic: the same inputs give bitwise-identical
+ *    outputs (no floating-point atomics; every sum has a fixed order).
+ */
+#ifndef EMAGPIE_H
+#define EMAGPIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct emagpie_ctx_s* emagpie_ctx;
+
+typedef enum {
+  EMAGPIE_OK = 0,
+  EMAGPIE_E_ARG = -1,         /* null pointer, bad enum, bad scalar            */
+  EMAGPIE_E_SHAPE = -2,       /* unsupported m / n / levels / minibatch        */
+  EMAGPIE_E_POSITION = -3,    /* a scan window leaves the object               */
+  EMAGPIE_E_DATA = -4,        /* NaN or Inf among the intensities              */
+  EMAGPIE_E_DEGENERATE = -5,  /* zero probe (normalisation impossible)         */
+  EMAGPIE_E_WORKSPACE = -6,   /* workspace missing, misaligned or too small    */
+  EMAGPIE_E_HIP = -7,         /* a HIP runtime call failed                     */
+  EMAGPIE_E_UNSUPPORTED = -8  /* valid request this build does not provide     */
+} emagpie_status;
+
+/* Execution path of emagpie_epoch (all give bitwise-identical results). */
+enum {
+  EMAGPIE_PATH_PLAIN = 0,  /* one launch per stage, HBM intermediates          */
+  EMAGPIE_PATH_FUSED = 1,  /* fused per-patch kernel + finalize kernel         */
+  EMAGPIE_PATH_GRAPH = 2,  /* FUSED launches replayed from a captured hipGraph */
+  EMAGPIE_PATH_PERSISTENT = 3 /* one cooperative launch per epoch, grid barriers */
+};
+
+enum { EMAGPIE_F32 = 0, EMAGPIE_F64 = 1 };
+
+typedef struct {
+  int32_t n;            /* object side (square object, n x n)                       */
+  int32_t m;            /* probe side: 32, 64 or 128                                */
+  int32_t n_pos;        /* number of scan positions N >= 1                          */
+  int32_t minibatch;    /* B >= 1 positions per update; B = 1 is the paper's
+                           sequential sweep (Sec. 2.2, Sec. 3)                       */
+  int32_t levels;       /* multigrid levels L: 1 (single level), 2 or 3 (Sec. 3.2)  */
+  float alpha;          /* alpha of u_Q = alpha(||Q||_inf^2 - |Q|^2), >= 0 (Sec. 4)  */
+  float alpha_z;        /* alpha_z of u_z; 1 = the ePIE probe step (Sec. 4)          */
+  int32_t update_probe; /* 1 blind (object and probe); 0 object only                */
+  int32_t path;         /* EMAGPIE_PATH_*                                           */
+  uint64_t seed;        /* scan-order generator seed                                */
+} emagpie_config;
+
+/* Bytes of device workspace a context with this configuration needs. */
+emagpie_status emagpie_workspace_size(const emagpie_config* cfg, size_t* bytes);
+
+/*
+ * Create a context.  positions_host: N x 2 int32 (row, col) top-left corners,
+ * copied; every window must satisfy 0 <= row, col <= n - m (Sec. 2.1, binary
+ * patch operator).  intensities_dev: N x m x m float32 measured intensities,
+ * unshifted (zero frequency at [0, 0]); copied into the workspace, so the
+ * caller may free it afterwards.  Negative counts act as zero amplitude
+ * (a = sqrt(max(d, 0)), Def. 2.1).  workspace_dev must be 256-byte aligned
+ * and at least emagpie_workspace_size() bytes; it stays owned by the caller
+ * and must outlive the context.  This call synchronises the stream: it
+ * returns EMAGPIE_E_DATA if any intensity is NaN or Inf.
+ */
+emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
+                            const int32_t* positions_host, const float* intensities_dev,
+                            void* workspace_dev, size_t workspace_bytes, void* stream);
+
+emagpie_status emagpie_destroy(emagpie_ctx ctx);
+
+/* dp_avg = sqrt(sum_ij mean_k d_k,ij) / m, computed in float64 at init (Sec. 4.1). */
+emagpie_status emagpie_dp_avg(emagpie_ctx ctx, double* dp_avg_host);
+
+/*
+ * Probe normalisation of Sec. 4.1: probe <- probe * dp_avg / ||probe||_2,
+ * in place on an m x m complex64 probe.  Synchronises the stream;
+ * EMAGPIE_E_DEGENERATE if the probe is zero.
+ */
+emagpie_status emagpie_normalize_probe(emagpie_ctx ctx, void* probe_dev, void* stream);
+
+/*
+ * One eMAGPIE minibatch update (Sec. 3, Prop. 3.2 joint step, Sec. 3.2
+ * multigrid object step), in place on obj_dev (n x n complex64) and
+ * probe_dev (m x m complex64).  batch_idx_dev: b int32 scan indices in
+ * [0, N) (distinct); all of them see the state at the start of the batch.
+ * The object step minimises the summed regularised surrogates of the batch
+ * (numerator / denominator accumulation in ascending slot order), the probe
+ * step the summed Eq. 8 surrogates; then the geometric-mean, phase-aligned
+ * joint step of Eq. 6 is applied once per touched object pixel and per probe
+ * pixel.  With b = 1 and levels = 1 this is exactly the paper's Prop. 3.2
+ * step.  If sampled_misfit_dev (one double) is not null, sum_k Phi_k at the
+ * batch-start state (Eq. 1 terms) is ADDED to it.  1 <= b <= minibatch.
+ */
+emagpie_status emagpie_step_minibatch(emagpie_ctx ctx, void* obj_dev, void* probe_dev,
+                                      const int32_t* batch_idx_dev, int32_t b,
+                                      double* sampled_misfit_dev, void* stream);
+
+/*
+ * One sweep over all N positions in consecutive minibatches of `minibatch`
+ * (the last may be shorter), in the scan order perm_dev (N int32, device) or,
+ * if perm_dev is null, in the library's order for (seed, epoch): a
+ * Fisher-Yates shuffle driven by SplitMix64 (see emagpie_permutation).  If
+ * sampled_misfit_dev is not null it is overwritten with the sum of the
+ * sampled misfits of the sweep.  The path in the config selects the launch
+ * strategy; results do not depend on it.
+ */
+emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, int64_t epoch,
+                             const int32_t* perm_dev, double* sampled_misfit_dev, void* stream);
+
+/*
+ * The MAGPIE object minimiser of Sec. 3.2 (closed forms after Eq. 15) for each
+ * patch of the batch, before any accumulation or joint step:
+ * zplus_dev[s] = z'_k + conj(Q)(R_k - Q z'_k)/(u + |Q|^2), b x m x m complex64.
+ * Inputs are not modified.
+ */
+emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
+                                const int32_t* batch_idx_dev, int32_t b, void* zplus_dev,
+                                void* stream);
+
+/* Exit-wave misfit Phi(Q, z) of Eq. 1 over all N positions, float64 sum, to misfit_dev. */
+emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
+                              double* misfit_dev, void* stream);
+
+/*
+ * Gradients of Phi (Sec. 2.1, CR calculus; gradient = d/dx + i d/dy):
+ * grad_obj = sum_k P_k^T conj(Q)(Q z_k - R_k) (n x n), grad_probe = sum_k
+ * conj(z_k)(Q z_k - R_k) (m x m), and Phi to misfit_dev.  dtype EMAGPIE_F32
+ * takes complex64 obj/probe/gradients, EMAGPIE_F64 complex128 (m <= 64).
+ * Gradients are overwritten, not accumulated.
+ */
+emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
+                            void* grad_obj_dev, void* grad_probe_dev, double* misfit_dev,
+                            int32_t dtype, void* stream);
+
+/*
+ * The library's scan order for (seed, epoch): Durstenfeld's Fisher-Yates
+ * shuffle of 0..n-1; SplitMix64 starting from seed XOR (epoch *
+ * 0x9E3779B97F4A7C15); slot i swaps with floor(x * (i + 1) / 2^64).  Host only.
+ */
+emagpie_status emagpie_permutation(uint64_t seed, int64_t epoch, int32_t n, int32_t* out_host);
+
+/*
+ * Kernel timing for benchmarks.  While enabled, HIP events are recorded on the
+ * caller's stream around every patch-stage launch group and every finalize
+ * launch of the plain and fused paths, and around every persistent-epoch
+ * launch (captured-graph replays are not instrumented).  Host only; events are
+ * library-owned host objects.
+ */
+emagpie_status emagpie_profile_enable(emagpie_ctx ctx, int32_t enable);
+
+/*
+ * Wait for the recorded events and return, per category (0 patch stage,
+ * 1 finalize, 2 persistent epoch), the summed milliseconds (ms3_host) and the
+ * number of timed launches (count3_host) since the previous read; then reset.
+ */
+emagpie_status emagpie_profile_read(emagpie_ctx ctx, double* ms3_host, int64_t* count3_host);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* emagpie_last_error(void);
+
+/* Library version string. */
+const char* emagpie_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMAGPIE_H */

@@ -1,0 +1,562 @@
+// libemagpie C ABI: validation, workspace carving, scan order, launch
+// strategies (plain, fused, captured hipGraph, persistent cooperative).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/emagpie.h"
+#include "launch.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+emagpie_status fail(emagpie_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define EMG_HIP(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(EMAGPIE_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+// SplitMix64 (Steele, Lea, Flood 2014; Vigna's reference definition)
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    s += kGamma;
+    uint64_t x = s;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+  }
+};
+
+void fisher_yates(uint64_t seed, int64_t epoch, int32_t n, int32_t* out) {
+  SplitMix64 g{seed ^ ((uint64_t)epoch * kGamma)};
+  for (int32_t i = 0; i < n; ++i) out[i] = i;
+  for (int32_t i = n - 1; i > 0; --i) {
+    const uint64_t x = g.next();
+    const int32_t j = (int32_t)(((unsigned __int128)x * (uint64_t)(i + 1)) >> 64);
+    const int32_t t = out[i];
+    out[i] = out[j];
+    out[j] = t;
+  }
+}
+
+struct Region {
+  size_t off, bytes;
+};
+
+struct Layout {
+  Region dperm, pos, perm, tw32, tw64, numer, pnum, pden, phi, stack, zmax, ubuf, Dbuf, scal,
+      phi_all, gz, gq;
+  int grad_chunk;
+  size_t total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(const emagpie_config& c) {
+  Layout L{};
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    Region r{cur, bytes};
+    cur += align256(bytes);
+    return r;
+  };
+  const size_t m2 = (size_t)c.m * c.m, N = (size_t)c.n_pos, B = (size_t)c.minibatch;
+  L.dperm = take(N * m2 * 4);
+  L.pos = take(N * 8);
+  L.perm = take(N * 4);
+  L.tw32 = take((size_t)c.m * 8);
+  L.tw64 = take((size_t)c.m * 16);
+  L.numer = take(B * m2 * 8);
+  L.pnum = take(B * m2 * 8);
+  L.pden = take(B * m2 * 4);
+  L.phi = take(B * 8);
+  L.stack = take(B * m2 * 8);
+  L.zmax = take(B * 4);
+  L.ubuf = take(m2 * 4);
+  L.Dbuf = take(m2 * 4);
+  L.scal = take(256);
+  L.phi_all = take(N * 8);
+  L.grad_chunk = (int)std::min<size_t>(N, c.m == 128 ? 256 : emg::kMaxSlots);
+  const size_t gel = c.m <= 64 ? 16 : 8;  // complex128 where the float64 gradient exists
+  L.gz = take((size_t)L.grad_chunk * m2 * gel);
+  L.gq = take((size_t)L.grad_chunk * m2 * gel);
+  L.total = cur;
+  return L;
+}
+
+emagpie_status check_config(const emagpie_config* c) {
+  if (!c) return fail(EMAGPIE_E_ARG, "null config");
+  if (c->m != 32 && c->m != 64 && c->m != 128)
+    return fail(EMAGPIE_E_SHAPE, "probe side m must be 32, 64 or 128");
+  if (c->n < c->m || c->n > 65536) return fail(EMAGPIE_E_SHAPE, "object side n must satisfy m <= n <= 65536");
+  if (c->n_pos < 1) return fail(EMAGPIE_E_SHAPE, "n_pos must be >= 1");
+  if (c->minibatch < 1 || c->minibatch > emg::kMaxSlots)
+    return fail(EMAGPIE_E_SHAPE, "minibatch must be in [1, 1024]");
+  if (c->levels < 1 || c->levels > 3) return fail(EMAGPIE_E_SHAPE, "levels must be 1, 2 or 3");
+  if (!(c->alpha >= 0.f) || !std::isfinite(c->alpha)) return fail(EMAGPIE_E_ARG, "alpha must be finite and >= 0");
+  if (!(c->alpha_z >= 0.f) || !std::isfinite(c->alpha_z))
+    return fail(EMAGPIE_E_ARG, "alpha_z must be finite and >= 0");
+  if (c->update_probe != 0 && c->update_probe != 1) return fail(EMAGPIE_E_ARG, "update_probe must be 0 or 1");
+  if (c->path < EMAGPIE_PATH_PLAIN || c->path > EMAGPIE_PATH_PERSISTENT)
+    return fail(EMAGPIE_E_ARG, "unknown path");
+  return EMAGPIE_OK;
+}
+
+}  // namespace
+
+struct emagpie_ctx_s {
+  emagpie_config cfg;
+  Layout lay;
+  uint8_t* ws;
+  float* dperm;
+  int2* pos;
+  int* perm;
+  float2* tw32;
+  double2* tw64;
+  float2 *numer, *pnum, *stack;
+  float *pden, *zmax, *ubuf, *Dbuf;
+  double *phi, *phi_all;
+  double* scal_d;  // [0] dp sum, [1] scratch
+  int* scal_i;     // [0] bad-data flag, [1] zero-probe flag
+  float* qqmax;
+  std::vector<int32_t> pos_host;
+  double dp_avg = 0.0;
+  int num_cus = 0;
+  int persist_grid = 0;
+  int32_t* perm_pinned[2] = {nullptr, nullptr};
+  hipEvent_t perm_ev[2] = {nullptr, nullptr};
+  int perm_slot = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  void* g_obj = nullptr;
+  void* g_probe = nullptr;
+  double* g_sampled = nullptr;
+  // kernel timing (category 0 patch stage, 1 finalize, 2 persistent epoch)
+  bool profile = false;
+  std::vector<hipEvent_t> ev[3];
+  size_t ev_used[3] = {0, 0, 0};
+};
+
+namespace {
+
+emg::StepArgs base_args(emagpie_ctx c, void* obj, void* probe) {
+  emg::StepArgs a{};
+  a.obj = static_cast<float2*>(obj);
+  a.n = c->cfg.n;
+  a.probe = static_cast<float2*>(probe);
+  a.dperm = c->dperm;
+  a.pos = c->pos;
+  a.alpha = c->cfg.alpha;
+  a.alpha_z = c->cfg.alpha_z;
+  a.update_probe = c->cfg.update_probe;
+  a.tw = c->tw32;
+  a.numer = c->numer;
+  a.pnum = c->pnum;
+  a.pden = c->pden;
+  a.phi = c->phi;
+  a.Dbuf = c->Dbuf;
+  a.stack = c->stack;
+  a.zmax = c->zmax;
+  a.ubuf = c->ubuf;
+  a.qqmax = c->qqmax;
+  return a;
+}
+
+// record one event of a (start, stop) pair for timing category `cat`
+emagpie_status mark(emagpie_ctx c, int cat, bool instrument, hipStream_t s) {
+  if (!c->profile || !instrument) return EMAGPIE_OK;
+  if (c->ev_used[cat] == c->ev[cat].size()) {
+    hipEvent_t e;
+    EMG_HIP(hipEventCreate(&e));
+    c->ev[cat].push_back(e);
+  }
+  EMG_HIP(hipEventRecord(c->ev[cat][c->ev_used[cat]++], s));
+  return EMAGPIE_OK;
+}
+
+#define EMG_OK(expr)                      \
+  do {                                    \
+    emagpie_status st_ = (expr);          \
+    if (st_ != EMAGPIE_OK) return st_;    \
+  } while (0)
+
+// enqueue one minibatch with the configured (non-graph) strategy
+emagpie_status enqueue_minibatch(emagpie_ctx c, const emg::StepArgs& a, bool plain, hipStream_t s,
+                                 bool instrument = true) {
+  const int m = c->cfg.m, L = c->cfg.levels;
+  EMG_OK(mark(c, 0, instrument, s));
+  if (plain) {
+    EMG_HIP(emg::launch_plain_step(m, L, a, s));
+  } else {
+    EMG_HIP(emg::launch_patch_step(m, L, a, s));
+  }
+  EMG_OK(mark(c, 0, instrument, s));
+  EMG_OK(mark(c, 1, instrument, s));
+  EMG_HIP(emg::launch_finalize(m, a, s));
+  EMG_OK(mark(c, 1, instrument, s));
+  return EMAGPIE_OK;
+}
+
+emagpie_status enqueue_sweep(emagpie_ctx c, void* obj, void* probe, double* sampled, bool plain,
+                             hipStream_t s, bool instrument = true) {
+  if (sampled) EMG_HIP(emg::launch_zero_doubles(sampled, 1, s));
+  const int N = c->cfg.n_pos, B = c->cfg.minibatch;
+  for (int start = 0; start < N; start += B) {
+    emg::StepArgs a = base_args(c, obj, probe);
+    a.idx = c->perm + start;
+    a.b = std::min(B, N - start);
+    a.sampled = sampled;
+    emagpie_status st = enqueue_minibatch(c, a, plain, s, instrument);
+    if (st != EMAGPIE_OK) return st;
+  }
+  return EMAGPIE_OK;
+}
+
+void drop_graph(emagpie_ctx c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* emagpie_version(void) { return "libemagpie 0.1 (gfx950)"; }
+
+const char* emagpie_last_error(void) { return g_err.c_str(); }
+
+emagpie_status emagpie_workspace_size(const emagpie_config* cfg, size_t* bytes) {
+  emagpie_status st = check_config(cfg);
+  if (st != EMAGPIE_OK) return st;
+  if (!bytes) return fail(EMAGPIE_E_ARG, "null output");
+  *bytes = make_layout(*cfg).total;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_permutation(uint64_t seed, int64_t epoch, int32_t n, int32_t* out_host) {
+  if (n < 0 || (n > 0 && !out_host)) return fail(EMAGPIE_E_ARG, "bad permutation arguments");
+  fisher_yates(seed, epoch, n, out_host);
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
+                            const int32_t* positions_host, const float* intensities_dev,
+                            void* workspace_dev, size_t workspace_bytes, void* stream) {
+  if (!out) return fail(EMAGPIE_E_ARG, "null context output");
+  *out = nullptr;
+  emagpie_status st = check_config(cfg);
+  if (st != EMAGPIE_OK) return st;
+  if (!positions_host || !intensities_dev) return fail(EMAGPIE_E_ARG, "null positions or intensities");
+  const emagpie_config c = *cfg;
+  for (int k = 0; k < c.n_pos; ++k) {
+    const int32_t r = positions_host[2 * k], q = positions_host[2 * k + 1];
+    if (r < 0 || q < 0 || r > c.n - c.m || q > c.n - c.m)
+      return fail(EMAGPIE_E_POSITION, "scan position " + std::to_string(k) + " = (" +
+                                          std::to_string(r) + ", " + std::to_string(q) +
+                                          ") leaves the object");
+  }
+  const Layout lay = make_layout(c);
+  if (!workspace_dev || (reinterpret_cast<uintptr_t>(workspace_dev) & 255))
+    return fail(EMAGPIE_E_WORKSPACE, "workspace missing or not 256-byte aligned");
+  if (workspace_bytes < lay.total)
+    return fail(EMAGPIE_E_WORKSPACE, "workspace too small: need " + std::to_string(lay.total) +
+                                         " bytes, got " + std::to_string(workspace_bytes));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  auto* ctx = new emagpie_ctx_s();
+  ctx->cfg = c;
+  ctx->lay = lay;
+  uint8_t* w = static_cast<uint8_t*>(workspace_dev);
+  ctx->ws = w;
+  ctx->dperm = reinterpret_cast<float*>(w + lay.dperm.off);
+  ctx->pos = reinterpret_cast<int2*>(w + lay.pos.off);
+  ctx->perm = reinterpret_cast<int*>(w + lay.perm.off);
+  ctx->tw32 = reinterpret_cast<float2*>(w + lay.tw32.off);
+  ctx->tw64 = reinterpret_cast<double2*>(w + lay.tw64.off);
+  ctx->numer = reinterpret_cast<float2*>(w + lay.numer.off);
+  ctx->pnum = reinterpret_cast<float2*>(w + lay.pnum.off);
+  ctx->pden = reinterpret_cast<float*>(w + lay.pden.off);
+  ctx->phi = reinterpret_cast<double*>(w + lay.phi.off);
+  ctx->stack = reinterpret_cast<float2*>(w + lay.stack.off);
+  ctx->zmax = reinterpret_cast<float*>(w + lay.zmax.off);
+  ctx->ubuf = reinterpret_cast<float*>(w + lay.ubuf.off);
+  ctx->Dbuf = reinterpret_cast<float*>(w + lay.Dbuf.off);
+  ctx->scal_d = reinterpret_cast<double*>(w + lay.scal.off);
+  ctx->scal_i = reinterpret_cast<int*>(w + lay.scal.off + 64);
+  ctx->qqmax = reinterpret_cast<float*>(w + lay.scal.off + 128);
+  ctx->phi_all = reinterpret_cast<double*>(w + lay.phi_all.off);
+  ctx->pos_host.assign(positions_host, positions_host + 2 * (size_t)c.n_pos);
+
+  auto bail = [&](emagpie_status e) {
+    emagpie_destroy(ctx);
+    return e;
+  };
+  auto hipfail = [&](hipError_t e, const char* what) {
+    fail(EMAGPIE_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return bail(EMAGPIE_E_HIP);
+  };
+  hipError_t e;
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hipfail(e, "hipGetDevice");
+  if ((e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hipfail(e, "hipDeviceGetAttribute");
+  if ((e = emg::persistent_grid_size(c.m, c.levels, ctx->num_cus, &ctx->persist_grid)) != hipSuccess)
+    return hipfail(e, "occupancy query");
+
+  // twiddles exp(-2 pi i j / m), evaluated in double on the host
+  std::vector<float2> t32(c.m);
+  std::vector<double2> t64(c.m);
+  for (int j = 0; j < c.m; ++j) {
+    const double ang = -2.0 * M_PI * (double)j / (double)c.m;
+    const double cr = std::cos(ang), ci = std::sin(ang);
+    t32[j] = make_float2((float)cr, (float)ci);
+    t64[j] = make_double2(cr, ci);
+  }
+  std::vector<int2> p2(c.n_pos);
+  for (int k = 0; k < c.n_pos; ++k) p2[k] = make_int2(positions_host[2 * k], positions_host[2 * k + 1]);
+  if ((e = hipMemcpyAsync(ctx->tw32, t32.data(), c.m * sizeof(float2), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hipfail(e, "upload twiddles");
+  if ((e = hipMemcpyAsync(ctx->tw64, t64.data(), c.m * sizeof(double2), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hipfail(e, "upload twiddles");
+  if ((e = hipMemcpyAsync(ctx->pos, p2.data(), c.n_pos * sizeof(int2), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hipfail(e, "upload positions");
+  if ((e = hipMemsetAsync(ctx->scal_i, 0, 64, s)) != hipSuccess) return hipfail(e, "clear flags");
+  if ((e = emg::launch_layout_intensities(c.m, intensities_dev, ctx->dperm, c.n_pos, ctx->phi_all,
+                                           ctx->scal_i, s)) != hipSuccess)
+    return hipfail(e, "layout intensities");
+  if ((e = emg::launch_sum_doubles(ctx->phi_all, c.n_pos, ctx->scal_d, s)) != hipSuccess)
+    return hipfail(e, "sum intensities");
+  double total = 0.0;
+  int bad = 0;
+  if ((e = hipMemcpyAsync(&total, ctx->scal_d, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hipfail(e, "read sum");
+  if ((e = hipMemcpyAsync(&bad, ctx->scal_i, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hipfail(e, "read flag");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hipfail(e, "synchronise init");
+  if (bad) {
+    fail(EMAGPIE_E_DATA, "intensities contain NaN or Inf");
+    return bail(EMAGPIE_E_DATA);
+  }
+  ctx->dp_avg = std::sqrt(total / (double)c.n_pos) / (double)c.m;
+
+  for (int i = 0; i < 2; ++i) {
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&ctx->perm_pinned[i]), sizeof(int32_t) * c.n_pos,
+                           hipHostMallocDefault)) != hipSuccess)
+      return hipfail(e, "pinned permutation buffer");
+    if ((e = hipEventCreateWithFlags(&ctx->perm_ev[i], hipEventDisableTiming)) != hipSuccess)
+      return hipfail(e, "event");
+  }
+  *out = ctx;
+  g_err.clear();
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_profile_enable(emagpie_ctx ctx, int32_t enable) {
+  if (!ctx) return fail(EMAGPIE_E_ARG, "null context");
+  ctx->profile = enable != 0;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_profile_read(emagpie_ctx ctx, double* ms3_host, int64_t* count3_host) {
+  if (!ctx || !ms3_host || !count3_host) return fail(EMAGPIE_E_ARG, "null argument");
+  for (int cat = 0; cat < 3; ++cat) {
+    double tot = 0.0;
+    const size_t used = ctx->ev_used[cat];
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      EMG_HIP(hipEventSynchronize(ctx->ev[cat][i + 1]));
+      float ms = 0.f;
+      EMG_HIP(hipEventElapsedTime(&ms, ctx->ev[cat][i], ctx->ev[cat][i + 1]));
+      tot += ms;
+    }
+    ms3_host[cat] = tot;
+    count3_host[cat] = (int64_t)(used / 2);
+    ctx->ev_used[cat] = 0;
+  }
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_destroy(emagpie_ctx ctx) {
+  if (!ctx) return EMAGPIE_OK;
+  drop_graph(ctx);
+  for (int cat = 0; cat < 3; ++cat) {
+    for (hipEvent_t e : ctx->ev[cat]) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
+  }
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (int i = 0; i < 2; ++i) {
+    if (ctx->perm_ev[i]) {
+      (void)hipEventSynchronize(ctx->perm_ev[i]);
+      (void)hipEventDestroy(ctx->perm_ev[i]);
+    }
+    if (ctx->perm_pinned[i]) (void)hipHostFree(ctx->perm_pinned[i]);
+  }
+  delete ctx;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_dp_avg(emagpie_ctx ctx, double* dp_avg_host) {
+  if (!ctx || !dp_avg_host) return fail(EMAGPIE_E_ARG, "null argument");
+  *dp_avg_host = ctx->dp_avg;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_normalize_probe(emagpie_ctx ctx, void* probe_dev, void* stream) {
+  if (!ctx || !probe_dev) return fail(EMAGPIE_E_ARG, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int flag = 0;
+  EMG_HIP(hipMemsetAsync(ctx->scal_i + 1, 0, sizeof(int), s));
+  EMG_HIP(emg::launch_normalize_probe(ctx->cfg.m, static_cast<float2*>(probe_dev), ctx->dp_avg,
+                                      ctx->scal_i + 1, s));
+  EMG_HIP(hipMemcpyAsync(&flag, ctx->scal_i + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  EMG_HIP(hipStreamSynchronize(s));
+  if (flag) return fail(EMAGPIE_E_DEGENERATE, "probe is zero; cannot normalise");
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_step_minibatch(emagpie_ctx ctx, void* obj_dev, void* probe_dev,
+                                      const int32_t* batch_idx_dev, int32_t b,
+                                      double* sampled_misfit_dev, void* stream) {
+  if (!ctx || !obj_dev || !probe_dev || !batch_idx_dev) return fail(EMAGPIE_E_ARG, "null argument");
+  if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
+  emg::StepArgs a = base_args(ctx, obj_dev, probe_dev);
+  a.idx = batch_idx_dev;
+  a.b = b;
+  a.sampled = sampled_misfit_dev;
+  return enqueue_minibatch(ctx, a, ctx->cfg.path == EMAGPIE_PATH_PLAIN, static_cast<hipStream_t>(stream));
+}
+
+emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, int64_t epoch,
+                             const int32_t* perm_dev, double* sampled_misfit_dev, void* stream) {
+  if (!ctx || !obj_dev || !probe_dev) return fail(EMAGPIE_E_ARG, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int N = ctx->cfg.n_pos;
+  if (perm_dev) {
+    EMG_HIP(hipMemcpyAsync(ctx->perm, perm_dev, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+  } else {
+    const int slot = ctx->perm_slot;
+    ctx->perm_slot ^= 1;
+    EMG_HIP(hipEventSynchronize(ctx->perm_ev[slot]));  // the copy that last read this buffer
+    fisher_yates(ctx->cfg.seed, epoch, N, ctx->perm_pinned[slot]);
+    EMG_HIP(hipMemcpyAsync(ctx->perm, ctx->perm_pinned[slot], sizeof(int32_t) * N,
+                           hipMemcpyHostToDevice, s));
+    EMG_HIP(hipEventRecord(ctx->perm_ev[slot], s));
+  }
+  switch (ctx->cfg.path) {
+    case EMAGPIE_PATH_PLAIN:
+      return enqueue_sweep(ctx, obj_dev, probe_dev, sampled_misfit_dev, true, s);
+    case EMAGPIE_PATH_FUSED:
+      return enqueue_sweep(ctx, obj_dev, probe_dev, sampled_misfit_dev, false, s);
+    case EMAGPIE_PATH_GRAPH: {
+      if (!ctx->gexec || ctx->g_obj != obj_dev || ctx->g_probe != probe_dev ||
+          ctx->g_sampled != sampled_misfit_dev) {
+        drop_graph(ctx);
+        if (!ctx->cap_stream) EMG_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        EMG_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        emagpie_status st =
+            enqueue_sweep(ctx, obj_dev, probe_dev, sampled_misfit_dev, false, ctx->cap_stream, false);
+        hipGraph_t g = nullptr;
+        hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (st != EMAGPIE_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return st;
+        }
+        if (ec != hipSuccess) return fail(EMAGPIE_E_HIP, std::string("capture: ") + hipGetErrorString(ec));
+        ctx->graph = g;
+        EMG_HIP(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+        ctx->g_obj = obj_dev;
+        ctx->g_probe = probe_dev;
+        ctx->g_sampled = sampled_misfit_dev;
+      }
+      EMG_HIP(hipGraphLaunch(ctx->gexec, s));
+      return EMAGPIE_OK;
+    }
+    case EMAGPIE_PATH_PERSISTENT: {
+      if (sampled_misfit_dev) EMG_HIP(emg::launch_zero_doubles(sampled_misfit_dev, 1, s));
+      emg::StepArgs a = base_args(ctx, obj_dev, probe_dev);
+      a.idx = ctx->perm;
+      a.b = std::min(ctx->cfg.minibatch, N);
+      a.sampled = sampled_misfit_dev;
+      EMG_OK(mark(ctx, 2, true, s));
+      EMG_HIP(emg::launch_persistent_epoch(ctx->cfg.m, ctx->cfg.levels, a, N, ctx->cfg.minibatch,
+                                           ctx->persist_grid, s));
+      EMG_OK(mark(ctx, 2, true, s));
+      return EMAGPIE_OK;
+    }
+    default:
+      return fail(EMAGPIE_E_ARG, "unknown path");
+  }
+}
+
+emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
+                                const int32_t* batch_idx_dev, int32_t b, void* zplus_dev,
+                                void* stream) {
+  if (!ctx || !obj_dev || !probe_dev || !batch_idx_dev || !zplus_dev)
+    return fail(EMAGPIE_E_ARG, "null argument");
+  if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
+  emg::StepArgs a = base_args(ctx, const_cast<void*>(obj_dev), const_cast<void*>(probe_dev));
+  a.idx = batch_idx_dev;
+  a.b = b;
+  a.phi = nullptr;
+  a.zplus = static_cast<float2*>(zplus_dev);
+  EMG_HIP(emg::launch_patch_step(ctx->cfg.m, ctx->cfg.levels, a, static_cast<hipStream_t>(stream)));
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
+                              double* misfit_dev, void* stream) {
+  if (!ctx || !obj_dev || !probe_dev || !misfit_dev) return fail(EMAGPIE_E_ARG, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  EMG_HIP(emg::launch_misfit_terms(ctx->cfg.m, static_cast<const float2*>(obj_dev), ctx->cfg.n,
+                                   static_cast<const float2*>(probe_dev), ctx->dperm, ctx->pos,
+                                   ctx->cfg.n_pos, ctx->tw32, ctx->phi_all, s));
+  EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
+                            void* grad_obj_dev, void* grad_probe_dev, double* misfit_dev,
+                            int32_t dtype, void* stream) {
+  if (!ctx || !obj_dev || !probe_dev || !grad_obj_dev || !grad_probe_dev)
+    return fail(EMAGPIE_E_ARG, "null argument");
+  if (dtype != EMAGPIE_F32 && dtype != EMAGPIE_F64) return fail(EMAGPIE_E_ARG, "dtype must be F32 or F64");
+  const bool f64 = dtype == EMAGPIE_F64;
+  if (f64 && ctx->cfg.m > 64) return fail(EMAGPIE_E_UNSUPPORTED, "float64 gradient needs m <= 64");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  emg::GradArgs g{};
+  g.obj = obj_dev;
+  g.n = ctx->cfg.n;
+  g.probe = probe_dev;
+  g.dperm = ctx->dperm;
+  g.pos = ctx->pos;
+  g.n_pos = ctx->cfg.n_pos;
+  g.chunk = ctx->lay.grad_chunk;
+  g.tw = f64 ? static_cast<const void*>(ctx->tw64) : static_cast<const void*>(ctx->tw32);
+  g.gobj = grad_obj_dev;
+  g.gprobe = grad_probe_dev;
+  g.gz_slots = ctx->ws + ctx->lay.gz.off;
+  g.gq_slots = ctx->ws + ctx->lay.gq.off;
+  g.phi_all = ctx->phi_all;
+  EMG_HIP(emg::launch_grad(ctx->cfg.m, f64, g, s));
+  if (misfit_dev) EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
+  return EMAGPIE_OK;
+}
+
+}  // extern "C"

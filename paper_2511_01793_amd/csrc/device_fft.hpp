@@ -1,0 +1,245 @@
+// LDS-resident 2-D FFT for one m x m complex tile per workgroup (gfx950).
+//
+// The transform is the unnormalised DFT of Sec. 2.1.  Each 1-D length-m
+// transform is a two-pass Cooley-Tukey factorisation m = R1 * R2 computed in
+// place in LDS: pass 1 does R2-point DFTs over stride-R1 elements and applies
+// the twiddles W_m^(n1 k2); pass 2 does R1-point DFTs over contiguous runs.
+// Both passes write back to the locations they read, so each pass needs one
+// barrier.  The forward transform therefore leaves the spectrum in
+// "transform order": LDS position p holds frequency p / R1 + R2 * (p % R1)
+// along each axis.  The inverse passes are the conjugate transposes in
+// reverse order, so they take transform order in and give natural order out.
+// Per-pixel work between the two transforms (the modulus projection) reads
+// its amplitudes in the same transform order, laid out once at init.
+//
+// LDS rows are padded by one element (row stride m + 1) so that the
+// line-parallel thread mapping used for both row and column passes is free
+// of bank conflicts.  Twiddles W_m^j = exp(-2 pi i j / m), j < m, come from a
+// table built on the host in double precision and staged in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emg {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> add(cx<T> a, cx<T> b) { return cx<T>{a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> sub(cx<T> a, cx<T> b) { return cx<T>{a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> mul(cx<T> a, cx<T> b) {
+  return cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return cx<T>{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return cx<T>{a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <typename T>
+__device__ __forceinline__ cx<T> conjg(cx<T> a) { return cx<T>{a.re, -a.im}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot90(cx<T> a) {
+  return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+// Factorisation and thread count per probe side.  The per-pixel phases give
+// each thread one 4 x 4 block, hence NT = m^2 / 16.
+template <int M> struct Plan;
+template <> struct Plan<32> { static constexpr int R1 = 8, R2 = 4, NT = 64; };
+template <> struct Plan<64> { static constexpr int R1 = 8, R2 = 8, NT = 256; };
+template <> struct Plan<128> { static constexpr int R1 = 16, R2 = 8, NT = 1024; };
+
+template <int M>
+__host__ __device__ constexpr int lds_stride() { return M + 1; }
+
+// frequency held at LDS position p after a forward pass pair
+template <int M>
+__host__ __device__ __forceinline__ int freq_of_pos(int p) {
+  return p / Plan<M>::R1 + Plan<M>::R2 * (p % Plan<M>::R1);
+}
+
+// ---------------------------------------------------------------------------
+// small DFTs in registers, forward sign exp(-2 pi i jk/R), inverse exp(+...)
+// ---------------------------------------------------------------------------
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+  cx<T> t = a;
+  a = add(t, b);
+  b = sub(t, b);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  cx<T> y0 = add(a0, a2), y1 = sub(a0, a2), y2 = add(a1, a3), y3 = rot90<T, INV>(sub(a1, a3));
+  a0 = add(y0, y2);
+  a2 = sub(y0, y2);
+  a1 = add(y1, y3);
+  a3 = sub(y1, y3);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  // even / odd split: X_k = E_k + W8^k O_k, X_{k+4} = E_k - W8^k O_k
+  cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<T, INV>(e0, e1, e2, e3);
+  dft4<T, INV>(o0, o1, o2, o3);
+  const T h = T(0.70710678118654752440084436210484903928);
+  // W8^1 = (h, -h) forward, (h, +h) inverse
+  cx<T> t1 = INV ? cx<T>{h * (o1.re - o1.im), h * (o1.re + o1.im)}
+                 : cx<T>{h * (o1.re + o1.im), h * (o1.im - o1.re)};
+  cx<T> t2 = rot90<T, INV>(o2);
+  // W8^3 = (-h, -h) forward, (-h, +h) inverse
+  cx<T> t3 = INV ? cx<T>{-h * (o3.re + o3.im), h * (o3.re - o3.im)}
+                 : cx<T>{h * (o3.im - o3.re), -h * (o3.re + o3.im)};
+  v[0] = add(e0, o0);
+  v[4] = sub(e0, o0);
+  v[1] = add(e1, t1);
+  v[5] = sub(e1, t1);
+  v[2] = add(e2, t2);
+  v[6] = sub(e2, t2);
+  v[3] = add(e3, t3);
+  v[7] = sub(e3, t3);
+}
+
+// 16-point DFT as two 8-point halves; W16^k = W_m^(k m/16) from the table.
+template <typename T, bool INV, int M>
+__device__ __forceinline__ void dft16(cx<T>* v, const cx<T>* tw) {
+  cx<T> e[8], o[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    e[j] = v[2 * j];
+    o[j] = v[2 * j + 1];
+  }
+  dft8<T, INV>(e);
+  dft8<T, INV>(o);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    cx<T> w = tw[k * (M / 16)];
+    if (INV) w = conjg(w);
+    cx<T> t = mul(w, o[k]);
+    v[k] = add(e[k], t);
+    v[k + 8] = sub(e[k], t);
+  }
+}
+
+template <typename T, bool INV, int R, int M>
+__device__ __forceinline__ void dft_small(cx<T>* v, const cx<T>* tw) {
+  if constexpr (R == 2) {
+    dft2<T, INV>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<T, INV>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    dft8<T, INV>(v);
+  } else {
+    static_assert(R == 16, "radix");
+    dft16<T, INV, M>(v, tw);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one in-place pass along rows (COLS = false) or columns (COLS = true)
+//   STRIDED: DFT over positions g + R1 * j (j < R2), group g = n1 < R1
+//   else   : DFT over positions R1 * g + j (j < R1), group g = k2 < R2
+//   forward strided pass multiplies output j by W^(g j) after the DFT;
+//   inverse strided pass multiplies input j by conj(W^(g j)) before it.
+// Work item w -> line = w % M (line fastest: conflict-free with stride M+1).
+// ---------------------------------------------------------------------------
+template <typename T, int M, bool INV, bool STRIDED, bool COLS>
+__device__ __forceinline__ void fft_pass(cx<T>* A, const cx<T>* tw, int tid) {
+  constexpr int R1 = Plan<M>::R1, R2 = Plan<M>::R2, NT = Plan<M>::NT;
+  constexpr int R = STRIDED ? R2 : R1;
+  constexpr int G = STRIDED ? R1 : R2;
+  constexpr int ITEMS = M * G;
+  constexpr int LS = lds_stride<M>();
+  static_assert(ITEMS % NT == 0, "items per thread");
+#pragma unroll
+  for (int it = 0; it < ITEMS / NT; ++it) {
+    const int w = tid + it * NT;
+    const int line = w % M;
+    const int g = w / M;
+    cx<T> v[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int p = STRIDED ? (g + R1 * j) : (R1 * g + j);
+      const int addr = COLS ? (p * LS + line) : (line * LS + p);
+      v[j] = A[addr];
+    }
+    if (STRIDED && INV) {
+#pragma unroll
+      for (int j = 1; j < R; ++j) v[j] = mul(conjg(tw[g * j]), v[j]);
+    }
+    dft_small<T, INV, R, M>(v, tw);
+    if (STRIDED && !INV) {
+#pragma unroll
+      for (int j = 1; j < R; ++j) v[j] = mul(tw[g * j], v[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int p = STRIDED ? (g + R1 * j) : (R1 * g + j);
+      const int addr = COLS ? (p * LS + line) : (line * LS + p);
+      A[addr] = v[j];
+    }
+  }
+}
+
+// Forward 2-D DFT: natural order in, transform order out.  Caller must have
+// synchronised after filling A; returns after a final barrier.
+template <typename T, int M>
+__device__ __forceinline__ void fft2_forward(cx<T>* A, const cx<T>* tw, int tid) {
+  fft_pass<T, M, false, true, false>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, false, false, false>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, false, true, true>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, false, false, true>(A, tw, tid);
+  __syncthreads();
+}
+
+// Inverse 2-D DFT without the 1/m^2 factor: transform order in, natural out.
+template <typename T, int M>
+__device__ __forceinline__ void fft2_inverse(cx<T>* A, const cx<T>* tw, int tid) {
+  fft_pass<T, M, true, false, true>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, true, true, true>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, true, false, false>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, true, true, false>(A, tw, tid);
+  __syncthreads();
+}
+
+// Principal complex square root (W. Kahan, "Branch Cuts for Complex
+// Elementary Functions", 1987: t = sqrt((|x| + |w|)/2), the other part from
+// y / (2t)), then the sign chosen so Re(root * conj(ref)) >= 0 (Eq. 6).
+template <typename T>
+__device__ __forceinline__ cx<T> aligned_sqrt(cx<T> ref, cx<T> plus) {
+  cx<T> w = mul(ref, plus);
+  T mag = sqrt(w.re * w.re + w.im * w.im);
+  if (mag == T(0)) return cx<T>{T(0), T(0)};
+  T t = sqrt((fabs(w.re) + mag) * T(0.5));
+  cx<T> s;
+  if (w.re >= T(0)) {
+    s = cx<T>{t, w.im / (T(2) * t)};
+  } else {
+    s = cx<T>{fabs(w.im) / (T(2) * t), copysign(t, w.im)};
+  }
+  if (s.re * ref.re + s.im * ref.im < T(0)) s = cx<T>{-s.re, -s.im};
+  return s;
+}
+
+}  // namespace emg

@@ -1,0 +1,87 @@
+// Host-side launchers for the eMAGPIE kernels (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emg {
+
+constexpr int kMaxSlots = 1024;  // patches per minibatch / gradient chunk
+
+struct StepArgs {
+  // state (complex64, interleaved)
+  float2* obj;       // n x n
+  int n;
+  float2* probe;     // m x m
+  // measured data in transform order, scan windows
+  const float* dperm;  // N x m x m
+  const int2* pos;     // N (row, col)
+  const int* idx;      // b slot -> scan index
+  int b;
+  float alpha, alpha_z;
+  int update_probe;
+  const float2* tw;  // m twiddles exp(-2 pi i j / m)
+  // per-slot products of the patch stage
+  float2* numer;     // b x m^2 object numerators conj(Q) R + u z'
+  float2* pnum;      // b x m^2 probe numerators conj(z) R + u_z Q
+  float* pden;       // b x m^2 probe denominators |z|^2 + u_z
+  double* phi;       // b sampled misfit terms
+  float* Dbuf;       // m^2 object denominators |Q|^2 + u (written by slot 0)
+  double* sampled;   // nullable accumulator of sum phi
+  float2* zplus;     // nullable: MAGPIE z+_k per slot (mg_cycle output)
+  // plain-path intermediates
+  float2* stack;     // b x m^2
+  float* zmax;       // b
+  float* ubuf;       // m^2
+  float* qqmax;      // 1
+};
+
+hipError_t launch_patch_step(int m, int L, const StepArgs& a, hipStream_t s);
+hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s);
+// plain path: the six patch-stage kernels (finalize is launched separately)
+hipError_t launch_plain_step(int m, int L, const StepArgs& a, hipStream_t s);
+
+// Persistent epoch: one cooperative launch runs every minibatch of a sweep.
+// a.idx must point at the full permutation (N entries); a.b is ignored.
+hipError_t persistent_grid_size(int m, int L, int num_cus, int* grid);
+hipError_t launch_persistent_epoch(int m, int L, const StepArgs& a, int n_pos, int minibatch,
+                                   int grid, hipStream_t s);
+
+// zero `count` doubles
+hipError_t launch_zero_doubles(double* p, int count, hipStream_t s);
+// out[0] = sum_{i < count} in[i] in a fixed order
+hipError_t launch_sum_doubles(const double* in, int count, double* out, hipStream_t s);
+
+// Copy intensities into transform order, flag non-finite values, and write
+// per-pattern float64 sums.
+hipError_t launch_layout_intensities(int m, const float* d, float* dperm, int n_pos,
+                                     double* pattern_sums, int* bad_flag, hipStream_t s);
+
+// probe <- probe * dp_avg / ||probe||; flag when the norm is zero
+hipError_t launch_normalize_probe(int m, float2* probe, double dp_avg, int* zero_flag,
+                                  hipStream_t s);
+
+// misfit terms of all patterns -> phi_all (N doubles), unreduced
+hipError_t launch_misfit_terms(int m, const float2* obj, int n, const float2* probe,
+                               const float* dperm, const int2* pos, int n_pos, const float2* tw,
+                               double* phi_all, hipStream_t s);
+
+// gradient of the misfit (float or double state), chunked over patterns
+struct GradArgs {
+  const void* obj;
+  int n;
+  const void* probe;
+  const float* dperm;
+  const int2* pos;
+  int n_pos;
+  int chunk;           // patterns per chunk (<= kMaxSlots)
+  const void* tw;      // twiddles in the gradient precision
+  void* gobj;          // n x n
+  void* gprobe;        // m x m
+  void* gz_slots;      // chunk x m^2
+  void* gq_slots;      // chunk x m^2
+  double* phi_all;     // N
+};
+hipError_t launch_grad(int m, bool f64, const GradArgs& g, hipStream_t s);
+
+}  // namespace emg

@@ -1,0 +1,267 @@
+"""Python binding of libemagpie (ctypes; argument marshalling only).
+
+Every step of the reconstruction runs in the HIP kernels of libemagpie.so.
+PyTorch supplies device memory (tensors) and the current HIP stream.  If the
+built library is missing this module raises at import of `lib()`; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libemagpie.so")
+
+PATHS = {"plain": 0, "fused": 1, "graph": 2, "persistent": 3}
+F32, F64 = 0, 1
+
+STATUS = {
+    0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_POSITION", -4: "E_DATA",
+    -5: "E_DEGENERATE", -6: "E_WORKSPACE", -7: "E_HIP", -8: "E_UNSUPPORTED",
+}
+
+EXPORTS = [
+    "emagpie_workspace_size", "emagpie_init", "emagpie_destroy", "emagpie_dp_avg",
+    "emagpie_normalize_probe", "emagpie_step_minibatch", "emagpie_epoch", "emagpie_mg_cycle",
+    "emagpie_misfit", "emagpie_grad", "emagpie_permutation", "emagpie_last_error",
+    "emagpie_version", "emagpie_profile_enable", "emagpie_profile_read",
+]
+
+
+class EmagpieError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("m", ctypes.c_int32), ("n_pos", ctypes.c_int32),
+        ("minibatch", ctypes.c_int32), ("levels", ctypes.c_int32),
+        ("alpha", ctypes.c_float), ("alpha_z", ctypes.c_float),
+        ("update_probe", ctypes.c_int32), ("path", ctypes.c_int32), ("seed", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libemagpie.so (built by `__graft_entry__.build()`); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    sz = ctypes.c_size_t
+    cfgp = ctypes.POINTER(Config)
+    sig = {
+        "emagpie_workspace_size": [cfgp, ctypes.POINTER(sz)],
+        "emagpie_init": [ctypes.POINTER(vp), cfgp, vp, vp, vp, sz, vp],
+        "emagpie_destroy": [vp],
+        "emagpie_dp_avg": [vp, ctypes.POINTER(ctypes.c_double)],
+        "emagpie_normalize_probe": [vp, vp, vp],
+        "emagpie_step_minibatch": [vp, vp, vp, vp, i32, vp, vp],
+        "emagpie_epoch": [vp, vp, vp, i64, vp, vp, vp],
+        "emagpie_mg_cycle": [vp, vp, vp, vp, i32, vp, vp],
+        "emagpie_misfit": [vp, vp, vp, vp, vp],
+        "emagpie_grad": [vp, vp, vp, vp, vp, vp, i32, vp],
+        "emagpie_permutation": [u64, i64, i32, vp],
+        "emagpie_profile_enable": [vp, i32],
+        "emagpie_profile_read": [vp, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.emagpie_last_error.restype = ctypes.c_char_p
+    L.emagpie_last_error.argtypes = []
+    L.emagpie_version.restype = ctypes.c_char_p
+    L.emagpie_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != 0:
+        raise EmagpieError(st, lib().emagpie_last_error().decode())
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def workspace_size(cfg: Config) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().emagpie_workspace_size(ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def permutation(seed: int, epoch: int, n: int) -> np.ndarray:
+    """The library's scan order for (seed, epoch) (host computation)."""
+    out = np.empty(n, dtype=np.int32)
+    _check(lib().emagpie_permutation(seed, epoch, n, out.ctypes.data))
+    return out
+
+
+def _expect(t: torch.Tensor, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or tuple(t.shape) != tuple(shape) \
+            or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {tuple(shape)}")
+
+
+class Reconstruction:
+    """One reconstruction problem bound to a libemagpie context.
+
+    positions: (N, 2) int (row, col) top-left corners; intensities: (N, m, m) float32 CUDA
+    tensor (unshifted).  The object (n x n) and probe (m x m) are complex64 CUDA tensors
+    owned by the caller and updated in place.
+    """
+
+    def __init__(self, positions, intensities: torch.Tensor, n: int, *, minibatch: int,
+                 levels: int = 1, alpha: float = 0.05, alpha_z: float = 1.0,
+                 update_probe: bool = True, path: str = "graph", seed: int = 0):
+        pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(-1, 2))
+        if intensities.dim() != 3 or intensities.dtype != torch.float32 or not intensities.is_cuda:
+            raise ValueError("intensities must be a (N, m, m) float32 CUDA tensor")
+        intensities = intensities.contiguous()
+        N, m, m2 = intensities.shape
+        if m != m2 or N != pos.shape[0]:
+            raise ValueError("intensities must be (N, m, m) with N = len(positions)")
+        self.n, self.m, self.n_pos = int(n), int(m), int(N)
+        self.cfg = Config(n=self.n, m=self.m, n_pos=self.n_pos, minibatch=int(minibatch),
+                          levels=int(levels), alpha=float(alpha), alpha_z=float(alpha_z),
+                          update_probe=int(bool(update_probe)), path=PATHS[path],
+                          seed=int(seed) & ((1 << 64) - 1))
+        nbytes = workspace_size(self.cfg)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=intensities.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.positions = pos
+        self._ctx = ctypes.c_void_p(None)
+        _check(lib().emagpie_init(ctypes.byref(self._ctx), ctypes.byref(self.cfg), pos.ctypes.data,
+                                  intensities.data_ptr(), self._ws_ptr, nbytes, _stream()))
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            torch.cuda.current_stream().synchronize()
+            lib().emagpie_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- timing -----------------------------------------------------------
+    def profile(self, enable: bool = True):
+        _check(lib().emagpie_profile_enable(self._ctx, int(bool(enable))))
+
+    def profile_read(self):
+        """{'patch': (ms, launches), 'finalize': (...), 'persistent': (...)} since the last read."""
+        ms = np.zeros(3, dtype=np.float64)
+        cnt = np.zeros(3, dtype=np.int64)
+        _check(lib().emagpie_profile_read(self._ctx, ms.ctypes.data, cnt.ctypes.data))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(["patch", "finalize", "persistent"])}
+
+    # -- operations -------------------------------------------------------
+    @property
+    def dp_avg(self) -> float:
+        out = ctypes.c_double(0)
+        _check(lib().emagpie_dp_avg(self._ctx, ctypes.byref(out)))
+        return out.value
+
+    def _state(self, obj, probe, dtype=torch.complex64):
+        _expect(obj, dtype, (self.n, self.n), "object")
+        _expect(probe, dtype, (self.m, self.m), "probe")
+
+    def normalize_probe(self, probe: torch.Tensor):
+        _expect(probe, torch.complex64, (self.m, self.m), "probe")
+        _check(lib().emagpie_normalize_probe(self._ctx, probe.data_ptr(), _stream()))
+
+    def _indices(self, idx) -> torch.Tensor:
+        t = torch.as_tensor(idx, dtype=torch.int32)
+        host = t.cpu().numpy() if t.is_cuda else t.numpy()
+        if host.ndim != 1 or host.size < 1 or host.size > self.cfg.minibatch:
+            raise ValueError("index list must be 1-D with 1..minibatch entries")
+        if host.min() < 0 or host.max() >= self.n_pos or len(set(host.tolist())) != host.size:
+            raise ValueError("indices must be distinct and in [0, N)")
+        return t.to(device="cuda").contiguous()
+
+    def step(self, obj, probe, idx, sampled: torch.Tensor | None = None):
+        self._state(obj, probe)
+        d_idx = self._indices(idx)
+        _check(lib().emagpie_step_minibatch(self._ctx, obj.data_ptr(), probe.data_ptr(),
+                                            d_idx.data_ptr(), d_idx.numel(), _ptr(sampled), _stream()))
+        return d_idx
+
+    def epoch(self, obj, probe, epoch: int, perm: torch.Tensor | None = None,
+              sampled: torch.Tensor | None = None):
+        self._state(obj, probe)
+        if perm is not None:
+            _expect(perm, torch.int32, (self.n_pos,), "perm")
+        _check(lib().emagpie_epoch(self._ctx, obj.data_ptr(), probe.data_ptr(), int(epoch),
+                                   _ptr(perm), _ptr(sampled), _stream()))
+
+    def mg_cycle(self, obj, probe, idx) -> torch.Tensor:
+        self._state(obj, probe)
+        d_idx = self._indices(idx)
+        out = torch.empty((d_idx.numel(), self.m, self.m), dtype=torch.complex64, device="cuda")
+        _check(lib().emagpie_mg_cycle(self._ctx, obj.data_ptr(), probe.data_ptr(), d_idx.data_ptr(),
+                                      d_idx.numel(), out.data_ptr(), _stream()))
+        return out
+
+    def misfit(self, obj, probe, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._state(obj, probe)
+        if out is None:
+            out = torch.empty((), dtype=torch.float64, device="cuda")
+        _check(lib().emagpie_misfit(self._ctx, obj.data_ptr(), probe.data_ptr(), out.data_ptr(),
+                                    _stream()))
+        return out
+
+    def grad(self, obj, probe):
+        """(grad_obj, grad_probe, Phi) with gradient = d/dx + i d/dy (float32 or float64)."""
+        f64 = obj.dtype == torch.complex128
+        self._state(obj, probe, torch.complex128 if f64 else torch.complex64)
+        gobj = torch.empty_like(obj)
+        gprobe = torch.empty_like(probe)
+        phi = torch.empty((), dtype=torch.float64, device="cuda")
+        _check(lib().emagpie_grad(self._ctx, obj.data_ptr(), probe.data_ptr(), gobj.data_ptr(),
+                                  gprobe.data_ptr(), phi.data_ptr(), F64 if f64 else F32, _stream()))
+        return gobj, gprobe, phi
+
+
+class AmplitudeMisfit(torch.autograd.Function):
+    """Phi(Q, z) of Eq. 1 with its hand-written adjoint (libemagpie grad kernels).
+
+    forward(obj, probe, rec) -> real scalar; backward returns grad_output times the CR
+    gradient d/dx + i d/dy, which is torch's convention for real losses of complex inputs.
+    Double backward is not supported.
+    """
+
+    @staticmethod
+    def forward(ctx, obj, probe, rec: Reconstruction):
+        gobj, gprobe, phi = rec.grad(obj.detach().contiguous(), probe.detach().contiguous())
+        ctx.save_for_backward(gobj, gprobe)
+        real = torch.float64 if obj.dtype == torch.complex128 else torch.float32
+        return phi.to(real)
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, g):
+        gobj, gprobe = ctx.saved_tensors
+        return g.to(gobj.real.dtype) * gobj, g.to(gprobe.real.dtype) * gprobe, None

@@ -1,0 +1,93 @@
+"""Host-side checks of the libemagpie C ABI (no GPU work is enqueued)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import emagpie_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+E = pytest.importorskip("paper_2511_01793_amd.emagpie")
+
+if not os.path.exists(E.LIB_PATH):
+    pytest.skip("libemagpie.so not built", allow_module_level=True)
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "emagpie.h")).read()
+    return sorted(set(re.findall(r"\b(emagpie_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = E.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(E.EXPORTS)
+    assert b"gfx950" in L.emagpie_version()
+
+
+def cfg(**kw):
+    base = dict(n=128, m=32, n_pos=100, minibatch=10, levels=1, alpha=0.01, alpha_z=1.0,
+                update_probe=1, path=0, seed=0)
+    base.update(kw)
+    return E.Config(**base)
+
+
+@pytest.mark.parametrize("bad, status", [
+    (dict(m=48), "E_SHAPE"), (dict(m=16), "E_SHAPE"), (dict(n=16), "E_SHAPE"),
+    (dict(levels=0), "E_SHAPE"), (dict(levels=4), "E_SHAPE"), (dict(minibatch=0), "E_SHAPE"),
+    (dict(minibatch=2048), "E_SHAPE"), (dict(n_pos=0), "E_SHAPE"),
+    (dict(alpha=float("nan")), "E_ARG"), (dict(alpha=-1.0), "E_ARG"), (dict(alpha_z=float("inf")), "E_ARG"),
+    (dict(path=9), "E_ARG"), (dict(update_probe=2), "E_ARG"),
+])
+def test_config_validation(bad, status):
+    with pytest.raises(E.EmagpieError) as ei:
+        E.workspace_size(cfg(**bad))
+    assert ei.value.name == status
+
+
+def test_workspace_size_scales_with_problem():
+    small = E.workspace_size(cfg())
+    big = E.workspace_size(cfg(n=512, m=64, n_pos=1600, minibatch=64, levels=2))
+    assert small > 100 * 32 * 32 * 4
+    # intensities copy alone: 1600 * 64^2 * 4 bytes
+    assert big > 1600 * 64 * 64 * 4 > small
+
+
+def _init(c, positions, ws_ptr, ws_bytes):
+    ctx = ctypes.c_void_p(None)
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32))
+    st = E.lib().emagpie_init(ctypes.byref(ctx), ctypes.byref(c), pos.ctypes.data, 0x1000,
+                              ws_ptr, ws_bytes, None)
+    return st, E.lib().emagpie_last_error().decode()
+
+
+def test_init_rejects_positions_outside_object():
+    c = cfg(n_pos=3)
+    ws = E.workspace_size(c)
+    for bad in ([0, 0], [96, 96], [97, 0], [0, -1]):
+        pos = [[0, 0], [10, 10], bad]
+        st, msg = _init(c, pos, 0x100000, ws)
+        if bad in ([0, 0], [96, 96]):
+            continue
+        assert E.STATUS[st] == "E_POSITION", msg
+        assert "scan position 2" in msg
+
+
+def test_init_rejects_bad_workspace():
+    c = cfg(n_pos=2)
+    ws = E.workspace_size(c)
+    st, msg = _init(c, [[0, 0], [1, 1]], 0x100010, ws)  # misaligned
+    assert E.STATUS[st] == "E_WORKSPACE"
+    st, msg = _init(c, [[0, 0], [1, 1]], 0x100000, ws - 1)  # too small
+    assert E.STATUS[st] == "E_WORKSPACE"
+    assert "too small" in msg
+
+
+def test_library_permutation_equals_oracle_bit_exactly():
+    for seed, epoch, n in [(0, 0, 1), (1, 0, 2), (1234567, 3, 100), (2**63 + 5, 99, 1600), (42, 7, 10000)]:
+        np.testing.assert_array_equal(E.permutation(seed, epoch, n), O.permutation(seed, epoch, n))

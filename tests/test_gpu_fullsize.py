@@ -1,0 +1,51 @@
+"""Parity at the benchmark's full size (512^2 object, 64^2 probe, 1600 positions, minibatch 64,
+two levels, Poisson 1e6 photons) in the launch configurations the benchmark times."""
+import numpy as np
+import pytest
+
+from oracle import emagpie_oracle as O
+from gpu_helpers import MISFIT_TOL, STEP_TOL, amps, host, init_state, make_rec, problem, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return problem("c2")
+
+
+@pytest.mark.parametrize("path", ["graph", "persistent"])
+def test_c2_minibatch_step_parity(c2, path):
+    p = c2
+    print("case: c2 step", path, flush=True)
+    rec = make_rec(p, path=path, seed=p.seed)
+    obj, probe = init_state(p, rec)
+    a = amps(p)
+    perm = O.permutation(p.seed, 0, p.n_pos)
+    for stage in range(2):
+        idx = perm[stage * 64:(stage + 1) * 64]
+        z0, q0 = host(obj), host(probe)
+        rec.step(obj, probe, idx)
+        torch.cuda.synchronize()
+        q1, z1, _ = O.step_minibatch(q0, z0, p.positions, a, idx, alpha=p.alpha, levels=2)
+        assert rel(host(obj), z1) < STEP_TOL, rel(host(obj), z1)
+        assert rel(host(probe), q1) < STEP_TOL, rel(host(probe), q1)
+        rec.epoch(obj, probe, 1 + stage)  # move to a mid-reconstruction state
+    rec.close()
+
+
+def test_c2_misfit_parity_and_sampled_misfit(c2):
+    p = c2
+    print("case: c2 misfit", flush=True)
+    rec = make_rec(p, path="graph", seed=p.seed)
+    obj, probe = init_state(p, rec)
+    a = amps(p)
+    s = torch.zeros((), dtype=torch.float64, device="cuda")
+    rec.epoch(obj, probe, 0, sampled=s)
+    phi = float(rec.misfit(obj, probe).item())
+    torch.cuda.synchronize()
+    ref = O.misfit(host(probe), host(obj), p.positions, a)
+    assert abs(phi - ref) <= MISFIT_TOL * ref
+    assert np.isfinite(float(s.item())) and float(s.item()) > phi
+    rec.close()

@@ -1,0 +1,353 @@
+"""HIP path vs FP64 oracle: element-wise parity through the C ABI on the GPU."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import emagpie_oracle as O
+from gpu_helpers import (EPOCH_TOL, GRAD32_TOL, GRAD64_TOL, MISFIT_TOL, STEP_TOL, amps, host,
+                         init_state, make_rec, problem, rel)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# a small problem that spans several object tiles and has a ragged last minibatch:
+# 100 x 100 object (tile 16 -> 7 x 7 tiles, last ragged), 32 x 32 probe, 5 x 5 raster
+def small(m=32, n=100, L=2, B=7, side=5, photons=None, seed=11):
+    step = max(1, (n - m - 2) // (side - 1))
+    return problem("tiny", n=n, m=m, scan=("raster", side, step, 1), photons=photons, B=B, L=L,
+                   alpha=0.05, seed=seed)
+
+
+def mid_state(p, rec, obj, probe, epochs=2):
+    """Move the GPU state away from the phase-free initial guess."""
+    for e in range(epochs):
+        rec.epoch(obj, probe, 100 + e)
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------ init
+
+def test_dp_avg_and_probe_normalisation():
+    p = small()
+    say("case: dp_avg/normalize", p.n, p.m)
+    rec = make_rec(p)
+    assert math.isclose(rec.dp_avg, O.dp_avg(p.intensities), rel_tol=1e-12)
+    probe = torch.from_numpy(p.probe_init).cuda()
+    rec.normalize_probe(probe)
+    torch.cuda.synchronize()
+    ref = O.normalise_probe(p.probe_init.astype(np.complex128), p.intensities)
+    assert rel(host(probe), ref) < 1e-6
+    rec.close()
+
+
+# ------------------------------------------------------------------ misfit (Eq. 1)
+
+@pytest.mark.parametrize("m", [32, 64])
+def test_misfit_parity(m):
+    p = small(m=m, n=3 * m + 5)
+    say("case: misfit", p.n, p.m)
+    rec = make_rec(p)
+    obj, probe = init_state(p, rec)
+    for stage in range(2):
+        phi = float(rec.misfit(obj, probe).item())
+        ref = O.misfit(host(probe), host(obj), p.positions, amps(p))
+        assert abs(phi - ref) <= MISFIT_TOL * ref, (stage, phi, ref)
+        mid_state(p, rec, obj, probe, 2)
+    rec.close()
+
+
+# ------------------------------------------------------------------ one step from identical state
+
+@pytest.mark.parametrize("m, L", [(32, 1), (32, 2), (32, 3), (64, 1), (64, 2), (64, 3)])
+@pytest.mark.parametrize("path", ["plain", "fused"])
+def test_step_parity_from_identical_state(m, L, path):
+    p = small(m=m, n=3 * m + 4, L=L, B=7)
+    say("case: step", p.n, p.m, L, path)
+    rec = make_rec(p, path=path)
+    obj, probe = init_state(p, rec)
+    a = amps(p)
+    rng = np.random.default_rng(m + L)
+    for stage in range(2):
+        idx = rng.choice(p.n_pos, size=7, replace=False).astype(np.int32)
+        z0, q0 = host(obj), host(probe)
+        sampled = torch.zeros((), dtype=torch.float64, device="cuda")
+        rec.step(obj, probe, idx, sampled=sampled)
+        torch.cuda.synchronize()
+        q1, z1, info = O.step_minibatch(q0, z0, p.positions, a, idx, alpha=p.alpha, levels=L)
+        assert rel(host(obj), z1) < STEP_TOL, (stage, rel(host(obj), z1))
+        assert rel(host(probe), q1) < STEP_TOL, (stage, rel(host(probe), q1))
+        ph = float(sampled.item())
+        assert abs(ph - info["sampled_misfit"]) <= MISFIT_TOL * info["sampled_misfit"]
+        mid_state(p, rec, obj, probe, 2)
+    rec.close()
+
+
+def test_single_position_step_is_the_paper_step():
+    # b = 1, one level: the Prop. 3.2 step, with untouched pixels left exactly as they were
+    p = small(m=32, n=80, L=1, B=1)
+    say("case: b=1 step", p.n)
+    rec = make_rec(p, path="fused")
+    obj, probe = init_state(p, rec)
+    mid_state(p, rec, obj, probe, 1)
+    z0, q0 = host(obj), host(probe)
+    k = 4
+    rec.step(obj, probe, [k])
+    torch.cuda.synchronize()
+    q1, z1, info = O.step_minibatch(q0, z0, p.positions, amps(p), [k], alpha=p.alpha, levels=1)
+    assert rel(host(obj), z1) < STEP_TOL and rel(host(probe), q1) < STEP_TOL
+    zg = obj.cpu().numpy()
+    t = info["touched"]
+    assert np.array_equal(zg[~t], z0[~t].astype(np.complex64))
+    rec.close()
+
+
+def test_non_blind_leaves_probe_bitwise():
+    p = small(m=32, n=90, L=2)
+    say("case: non-blind")
+    rec = make_rec(p, update_probe=False)
+    obj, probe = init_state(p, rec)
+    q0 = probe.clone()
+    rec.epoch(obj, probe, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(probe, q0)
+    rec.close()
+
+
+def test_probe_size_128_three_levels():
+    p = problem("tiny", n=200, m=128, scan=("raster", 3, 34, 1), photons=1e7, B=4, L=3,
+                alpha=0.05, seed=5)
+    say("case: m=128 L=3", p.n)
+    rec = make_rec(p, path="fused")
+    obj, probe = init_state(p, rec)
+    a = amps(p)
+    for stage in range(2):
+        idx = np.array([8, 0, 4, 2][: 4], dtype=np.int32)
+        z0, q0 = host(obj), host(probe)
+        rec.step(obj, probe, idx)
+        torch.cuda.synchronize()
+        q1, z1, _ = O.step_minibatch(q0, z0, p.positions, a, idx, alpha=p.alpha, levels=3)
+        assert rel(host(obj), z1) < STEP_TOL and rel(host(probe), q1) < STEP_TOL
+        mid_state(p, rec, obj, probe, 1)
+    zp = rec.mg_cycle(obj, probe, [1, 7])
+    torch.cuda.synchronize()
+    z0, q0 = host(obj), host(probe)
+    for j, k in enumerate([1, 7]):
+        r0, c0 = p.positions[k]
+        zk = z0[r0:r0 + 128, c0:c0 + 128]
+        R = O.revised_exit_wave(q0, zk, a[k])
+        ref = O.magpie_object_step(q0, zk, R, O.probe_regulariser(q0, p.alpha), 3)
+        assert rel(host(zp[j]), ref) < STEP_TOL
+    rec.close()
+
+
+# ------------------------------------------------------------------ multigrid object step
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+def test_mg_cycle_parity(L):
+    p = small(m=64, n=200, L=L, B=5)
+    say("case: mg_cycle", L)
+    rec = make_rec(p)
+    obj, probe = init_state(p, rec)
+    mid_state(p, rec, obj, probe, 2)
+    idx = [3, 17, 0, 24, 9]
+    zp = rec.mg_cycle(obj, probe, idx)
+    torch.cuda.synchronize()
+    z0, q0 = host(obj), host(probe)
+    a = amps(p)
+    u = O.probe_regulariser(q0, p.alpha)
+    for j, k in enumerate(idx):
+        r0, c0 = p.positions[k]
+        zk = z0[r0:r0 + 64, c0:c0 + 64]
+        R = O.revised_exit_wave(q0, zk, a[k])
+        assert rel(host(zp[j]), O.magpie_object_step(q0, zk, R, u, L)) < STEP_TOL, k
+    rec.close()
+
+
+# ------------------------------------------------------------------ epochs
+
+def test_epoch_parity_and_library_scan_order():
+    p = small(m=32, n=100, L=2, B=7)  # 25 positions: 3 batches of 7 and a ragged one of 4
+    say("case: epoch")
+    rec = make_rec(p, path="graph", seed=99)
+    obj, probe = init_state(p, rec)
+    a = amps(p)
+    for e in range(3):
+        z0, q0 = host(obj), host(probe)
+        sampled = torch.zeros((), dtype=torch.float64, device="cuda")
+        rec.epoch(obj, probe, e, sampled=sampled)
+        torch.cuda.synchronize()
+        q1, z1, samp = O.run_epoch(q0, z0, p.positions, a, seed=99, epoch=e, minibatch=7,
+                                   alpha=p.alpha, levels=2)
+        assert rel(host(obj), z1) < EPOCH_TOL, (e, rel(host(obj), z1))
+        assert rel(host(probe), q1) < EPOCH_TOL, (e, rel(host(probe), q1))
+        assert abs(float(sampled.item()) - samp) <= MISFIT_TOL * samp
+    rec.close()
+
+
+def test_all_paths_bitwise_identical_and_deterministic():
+    p = small(m=32, n=100, L=2, B=7)
+    say("case: paths")
+    finals = {}
+    for path in ["plain", "fused", "graph", "persistent", "graph"]:
+        rec = make_rec(p, path=path, seed=5)
+        obj, probe = init_state(p, rec)
+        s = torch.zeros((), dtype=torch.float64, device="cuda")
+        for e in range(3):
+            rec.epoch(obj, probe, e, sampled=s)
+        torch.cuda.synchronize()
+        res = (obj.cpu().numpy().copy(), probe.cpu().numpy().copy(), float(s.item()))
+        if path in finals:
+            prev = finals[path]
+            assert np.array_equal(prev[0], res[0]) and np.array_equal(prev[1], res[1])
+        finals[path] = res
+        rec.close()
+    ref = finals["plain"]
+    for path, res in finals.items():
+        assert np.array_equal(res[0], ref[0]), path
+        assert np.array_equal(res[1], ref[1]), path
+        assert res[2] == ref[2], path
+
+
+def test_explicit_permutation_and_edges():
+    # windows on the object border (row or col 0 and n - m) and a caller-supplied order
+    n, m = 96, 32
+    pos = np.array([[0, 0], [0, 64], [64, 0], [64, 64], [30, 31], [1, 63]], dtype=np.int32)
+    rng = np.random.default_rng(2)
+    z_true = (0.9 + 0.1 * rng.random((n, n))) * np.exp(1j * rng.uniform(-1, 1, (n, n)))
+    from paper_2511_01793_amd import synth
+    q_true = synth.true_probe(m)
+    d = synth.simulate_intensities(q_true, z_true, pos).astype(np.float32)
+    import paper_2511_01793_amd.emagpie as E
+    say("case: edges")
+    rec = E.Reconstruction(pos, torch.from_numpy(d).cuda(), n, minibatch=4, levels=2, alpha=0.05,
+                           path="fused", seed=0)
+    obj = torch.ones((n, n), dtype=torch.complex64, device="cuda")
+    probe = torch.from_numpy(synth.initial_probe(m).astype(np.complex64)).cuda()
+    rec.normalize_probe(probe)
+    # The initial guess (z = 1, real probe symmetric about the window centre) has Fourier
+    # bins that vanish in exact arithmetic (the Nyquist row and column), where every phase
+    # is a valid projection; with this high-frequency object their amplitudes are large, so
+    # the comparison starts from the state after one sweep, where no bin is degenerate.
+    rec.epoch(obj, probe, 7)
+    perm = torch.tensor([5, 3, 0, 1, 4, 2], dtype=torch.int32, device="cuda")
+    z0, q0 = host(obj), host(probe)
+    rec.epoch(obj, probe, 0, perm=perm)
+    torch.cuda.synchronize()
+    q1, z1, _ = O.run_epoch(q0, z0, pos, O.amplitudes(d), seed=0, epoch=0, minibatch=4,
+                            alpha=0.05, levels=2, perm=perm.cpu().numpy())
+    assert rel(host(obj), z1) < EPOCH_TOL and rel(host(probe), q1) < EPOCH_TOL
+    rec.close()
+
+
+def test_c1_end_to_end_final_misfit_within_one_percent():
+    p = problem("c1")
+    say("case: c1 end-to-end")
+    rec = make_rec(p, path="graph", seed=p.seed)
+    obj, probe = init_state(p, rec)
+    q, z = host(probe), host(obj)
+    a = amps(p)
+    for e in range(p.epochs):
+        rec.epoch(obj, probe, e)
+        q, z, _ = O.run_epoch(q, z, p.positions, a, seed=p.seed, epoch=e, minibatch=p.minibatch,
+                              alpha=p.alpha, levels=p.levels)
+    phi = float(rec.misfit(obj, probe).item())
+    ref = O.misfit(q, z, p.positions, a)
+    say("c1 misfit gpu", phi, "oracle", ref)
+    assert abs(phi - ref) <= 0.01 * ref
+    rec.close()
+
+
+# ------------------------------------------------------------------ gradient (Sec. 2.1)
+
+@pytest.mark.parametrize("f64", [False, True])
+def test_grad_parity(f64):
+    p = problem("tiny", n=120, m=64, scan=("raster", 4, 18, 1), photons=1e6, B=16, L=1,
+                alpha=0.05, seed=21)
+    say("case: grad", f64)
+    rec = make_rec(p)
+    obj, probe = init_state(p, rec)
+    mid_state(p, rec, obj, probe, 2)
+    if f64:
+        obj, probe = obj.to(torch.complex128), probe.to(torch.complex128)
+    gz, gq, phi = rec.grad(obj, probe)
+    torch.cuda.synchronize()
+    rz, rq, rphi = O.gradients(host(probe), host(obj), p.positions, amps(p))
+    tol = GRAD64_TOL if f64 else GRAD32_TOL
+    assert rel(host(gz), rz) < tol, rel(host(gz), rz)
+    assert rel(host(gq), rq) < tol, rel(host(gq), rq)
+    assert abs(float(phi.item()) - rphi) <= (1e-12 if f64 else MISFIT_TOL) * rphi
+    rec.close()
+
+
+def test_amplitude_misfit_autograd_and_finite_differences():
+    import paper_2511_01793_amd.emagpie as E
+    p = problem("tiny", n=90, m=32, scan=("raster", 4, 18, 1), photons=None, B=16, L=1,
+                alpha=0.05, seed=23)
+    say("case: autograd")
+    rec = make_rec(p)
+    obj, probe = init_state(p, rec)
+    mid_state(p, rec, obj, probe, 1)
+    o64 = obj.to(torch.complex128).requires_grad_(True)
+    q64 = probe.to(torch.complex128).requires_grad_(True)
+    phi = E.AmplitudeMisfit.apply(o64, q64, rec)
+    phi.backward()
+    gz, gq, _ = rec.grad(o64.detach(), q64.detach())
+    assert torch.equal(o64.grad, gz) and torch.equal(q64.grad, gq)
+    # central differences of the float64 misfit along random directions
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    for _ in range(3):
+        vz = torch.from_numpy(rng.standard_normal(o64.shape) + 1j * rng.standard_normal(o64.shape)).cuda()
+        vq = torch.from_numpy(rng.standard_normal(q64.shape) + 1j * rng.standard_normal(q64.shape)).cuda()
+        with torch.no_grad():
+            fp = rec.grad(o64 + h * vz, q64 + h * vq)[2].item()
+            fm = rec.grad(o64 - h * vz, q64 - h * vq)[2].item()
+        fd = (fp - fm) / (2 * h)
+        an = float((torch.sum(torch.conj(gz) * vz) + torch.sum(torch.conj(gq) * vq)).real.item())
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+    # gradient matching of Prop. 3.1: the frozen-surrogate gradient equals grad Phi
+    zk = host(o64.detach())
+    qk = host(q64.detach())
+    k = 3
+    r0, c0 = p.positions[k]
+    R = O.revised_exit_wave(qk, zk[r0:r0 + 32, c0:c0 + 32], amps(p)[k])
+    # Phi~ with R frozen has gradient conj(Q)(Q z_k - R) on patch k; sum over all k is grad Phi
+    gsum = np.zeros_like(zk)
+    for kk, (rr, cc) in enumerate(p.positions):
+        Rk = O.revised_exit_wave(qk, zk[rr:rr + 32, cc:cc + 32], amps(p)[kk])
+        gsum[rr:rr + 32, cc:cc + 32] += np.conj(qk) * (qk * zk[rr:rr + 32, cc:cc + 32] - Rk)
+    assert rel(host(gz), gsum) < GRAD64_TOL
+    assert R.shape == (32, 32)
+    rec.close()
+
+
+# ------------------------------------------------------------------ error paths on the device
+
+def test_non_finite_intensities_rejected():
+    import paper_2511_01793_amd.emagpie as E
+    p = small()
+    d = p.intensities.copy()
+    d[3, 5, 7] = np.nan
+    say("case: nan")
+    with pytest.raises(E.EmagpieError) as ei:
+        E.Reconstruction(p.positions, torch.from_numpy(d).cuda(), p.n, minibatch=7, levels=2)
+    assert ei.value.name == "E_DATA"
+
+
+def test_zero_probe_normalisation_rejected():
+    import paper_2511_01793_amd.emagpie as E
+    p = small()
+    say("case: zero probe")
+    rec = make_rec(p)
+    probe = torch.zeros((p.m, p.m), dtype=torch.complex64, device="cuda")
+    with pytest.raises(E.EmagpieError) as ei:
+        rec.normalize_probe(probe)
+    assert ei.value.name == "E_DEGENERATE"
+    rec.close()
