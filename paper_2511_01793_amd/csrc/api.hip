@@ -57,8 +57,8 @@ struct Region {
 };
 
 struct Layout {
-  Region dperm, pos, perm, tw32, tw64, numer, pnum, pden, phi, stack, zmax, ubuf, Dbuf, scal,
-      phi_all, gz, gq;
+  Region dperm, pos, slots, tw32, tw64, numer, pnum, pden, phi, stack, zmax, ubuf, Dbuf, scal,
+      bar, phi_all, gz, gq;
   int grad_chunk;
   size_t total;
 };
@@ -76,7 +76,7 @@ Layout make_layout(const emagpie_config& c) {
   const size_t m2 = (size_t)c.m * c.m, N = (size_t)c.n_pos, B = (size_t)c.minibatch;
   L.dperm = take(N * m2 * 4);
   L.pos = take(N * 8);
-  L.perm = take(N * 4);
+  L.slots = take(std::max(N, B) * 16);
   L.tw32 = take((size_t)c.m * 8);
   L.tw64 = take((size_t)c.m * 16);
   L.numer = take(B * m2 * 8);
@@ -88,6 +88,7 @@ Layout make_layout(const emagpie_config& c) {
   L.ubuf = take(m2 * 4);
   L.Dbuf = take(m2 * 4);
   L.scal = take(256);
+  L.bar = take(256);
   L.phi_all = take(N * 8);
   L.grad_chunk = (int)std::min<size_t>(N, c.m == 128 ? 256 : emg::kMaxSlots);
   const size_t gel = c.m <= 64 ? 16 : 8;  // complex128 where the float64 gradient exists
@@ -123,7 +124,7 @@ struct emagpie_ctx_s {
   uint8_t* ws;
   float* dperm;
   int2* pos;
-  int* perm;
+  int4* slots;  // per slot of the current sweep / batch: (k, row, col, 0)
   float2* tw32;
   double2* tw64;
   float2 *numer, *pnum, *stack;
@@ -133,10 +134,14 @@ struct emagpie_ctx_s {
   int* scal_i;     // [0] bad-data flag, [1] zero-probe flag
   float* qqmax;
   std::vector<int32_t> pos_host;
+  std::vector<int32_t> perm_host;
   double dp_avg = 0.0;
   int num_cus = 0;
   int persist_grid = 0;
-  int32_t* perm_pinned[2] = {nullptr, nullptr};
+  unsigned* bar = nullptr;  // persistent-kernel barrier counter (grows monotonically)
+  unsigned bar_base = 0;
+  bool bar_ready = false;
+  int4* perm_pinned[2] = {nullptr, nullptr};
   hipEvent_t perm_ev[2] = {nullptr, nullptr};
   int perm_slot = 0;
   hipStream_t cap_stream = nullptr;
@@ -217,7 +222,7 @@ emagpie_status enqueue_sweep(emagpie_ctx c, void* obj, void* probe, double* samp
   const int N = c->cfg.n_pos, B = c->cfg.minibatch;
   for (int start = 0; start < N; start += B) {
     emg::StepArgs a = base_args(c, obj, probe);
-    a.idx = c->perm + start;
+    a.slot = c->slots + start;
     a.b = std::min(B, N - start);
     a.sampled = sampled;
     emagpie_status st = enqueue_minibatch(c, a, plain, s, instrument);
@@ -286,7 +291,7 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   ctx->ws = w;
   ctx->dperm = reinterpret_cast<float*>(w + lay.dperm.off);
   ctx->pos = reinterpret_cast<int2*>(w + lay.pos.off);
-  ctx->perm = reinterpret_cast<int*>(w + lay.perm.off);
+  ctx->slots = reinterpret_cast<int4*>(w + lay.slots.off);
   ctx->tw32 = reinterpret_cast<float2*>(w + lay.tw32.off);
   ctx->tw64 = reinterpret_cast<double2*>(w + lay.tw64.off);
   ctx->numer = reinterpret_cast<float2*>(w + lay.numer.off);
@@ -301,6 +306,7 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   ctx->scal_i = reinterpret_cast<int*>(w + lay.scal.off + 64);
   ctx->qqmax = reinterpret_cast<float*>(w + lay.scal.off + 128);
   ctx->phi_all = reinterpret_cast<double*>(w + lay.phi_all.off);
+  ctx->bar = reinterpret_cast<unsigned*>(w + lay.bar.off);
   ctx->pos_host.assign(positions_host, positions_host + 2 * (size_t)c.n_pos);
 
   auto bail = [&](emagpie_status e) {
@@ -356,7 +362,7 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   ctx->dp_avg = std::sqrt(total / (double)c.n_pos) / (double)c.m;
 
   for (int i = 0; i < 2; ++i) {
-    if ((e = hipHostMalloc(reinterpret_cast<void**>(&ctx->perm_pinned[i]), sizeof(int32_t) * c.n_pos,
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&ctx->perm_pinned[i]), sizeof(int4) * c.n_pos,
                            hipHostMallocDefault)) != hipSuccess)
       return hipfail(e, "pinned permutation buffer");
     if ((e = hipEventCreateWithFlags(&ctx->perm_ev[i], hipEventDisableTiming)) != hipSuccess)
@@ -436,11 +442,13 @@ emagpie_status emagpie_step_minibatch(emagpie_ctx ctx, void* obj_dev, void* prob
                                       double* sampled_misfit_dev, void* stream) {
   if (!ctx || !obj_dev || !probe_dev || !batch_idx_dev) return fail(EMAGPIE_E_ARG, "null argument");
   if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  EMG_HIP(emg::launch_slot_info(batch_idx_dev, ctx->pos, ctx->cfg.n_pos, ctx->slots, b, s));
   emg::StepArgs a = base_args(ctx, obj_dev, probe_dev);
-  a.idx = batch_idx_dev;
+  a.slot = ctx->slots;
   a.b = b;
   a.sampled = sampled_misfit_dev;
-  return enqueue_minibatch(ctx, a, ctx->cfg.path == EMAGPIE_PATH_PLAIN, static_cast<hipStream_t>(stream));
+  return enqueue_minibatch(ctx, a, ctx->cfg.path == EMAGPIE_PATH_PLAIN, s);
 }
 
 emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, int64_t epoch,
@@ -449,14 +457,20 @@ emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, in
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int N = ctx->cfg.n_pos;
   if (perm_dev) {
-    EMG_HIP(hipMemcpyAsync(ctx->perm, perm_dev, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+    EMG_HIP(emg::launch_slot_info(perm_dev, ctx->pos, N, ctx->slots, N, s));
   } else {
+    // scan order and window corners gathered on the host, one upload per sweep
     const int slot = ctx->perm_slot;
     ctx->perm_slot ^= 1;
     EMG_HIP(hipEventSynchronize(ctx->perm_ev[slot]));  // the copy that last read this buffer
-    fisher_yates(ctx->cfg.seed, epoch, N, ctx->perm_pinned[slot]);
-    EMG_HIP(hipMemcpyAsync(ctx->perm, ctx->perm_pinned[slot], sizeof(int32_t) * N,
-                           hipMemcpyHostToDevice, s));
+    ctx->perm_host.resize(N);
+    fisher_yates(ctx->cfg.seed, epoch, N, ctx->perm_host.data());
+    int4* dst = ctx->perm_pinned[slot];
+    for (int j = 0; j < N; ++j) {
+      const int k = ctx->perm_host[j];
+      dst[j] = make_int4(k, ctx->pos_host[2 * k], ctx->pos_host[2 * k + 1], 0);
+    }
+    EMG_HIP(hipMemcpyAsync(ctx->slots, dst, sizeof(int4) * N, hipMemcpyHostToDevice, s));
     EMG_HIP(hipEventRecord(ctx->perm_ev[slot], s));
   }
   switch (ctx->cfg.path) {
@@ -491,13 +505,22 @@ emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, in
     case EMAGPIE_PATH_PERSISTENT: {
       if (sampled_misfit_dev) EMG_HIP(emg::launch_zero_doubles(sampled_misfit_dev, 1, s));
       emg::StepArgs a = base_args(ctx, obj_dev, probe_dev);
-      a.idx = ctx->perm;
+      a.slot = ctx->slots;
       a.b = std::min(ctx->cfg.minibatch, N);
       a.sampled = sampled_misfit_dev;
+      if (!ctx->bar_ready || ctx->bar_base > (1u << 30)) {
+        EMG_HIP(emg::launch_zero_u32(ctx->bar, s));
+        ctx->bar_base = 0;
+        ctx->bar_ready = true;
+      }
+      int used = 0;
       EMG_OK(mark(ctx, 2, true, s));
       EMG_HIP(emg::launch_persistent_epoch(ctx->cfg.m, ctx->cfg.levels, a, N, ctx->cfg.minibatch,
-                                           ctx->persist_grid, s));
+                                           ctx->persist_grid, ctx->bar, ctx->bar_base,
+                                           ctx->scal_i + 2, &used, s));
       EMG_OK(mark(ctx, 2, true, s));
+      const unsigned nbatch = (unsigned)((N + ctx->cfg.minibatch - 1) / ctx->cfg.minibatch);
+      ctx->bar_base += 2u * nbatch * (unsigned)used;
       return EMAGPIE_OK;
     }
     default:
@@ -511,12 +534,14 @@ emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void
   if (!ctx || !obj_dev || !probe_dev || !batch_idx_dev || !zplus_dev)
     return fail(EMAGPIE_E_ARG, "null argument");
   if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  EMG_HIP(emg::launch_slot_info(batch_idx_dev, ctx->pos, ctx->cfg.n_pos, ctx->slots, b, s));
   emg::StepArgs a = base_args(ctx, const_cast<void*>(obj_dev), const_cast<void*>(probe_dev));
-  a.idx = batch_idx_dev;
+  a.slot = ctx->slots;
   a.b = b;
   a.phi = nullptr;
   a.zplus = static_cast<float2*>(zplus_dev);
-  EMG_HIP(emg::launch_patch_step(ctx->cfg.m, ctx->cfg.levels, a, static_cast<hipStream_t>(stream)));
+  EMG_HIP(emg::launch_patch_step(ctx->cfg.m, ctx->cfg.levels, a, s));
   return EMAGPIE_OK;
 }
 

@@ -8,17 +8,19 @@
 // block-ratio form), the object numerator conj(Q) R + u z' (Eq. 7 / Eq. 9 as
 // a numerator over a denominator), and the probe numerator / denominator of
 // Eq. 8.  A finalize stage then sums the numerators over the batch in
-// ascending slot order (owner-computes object tiles, fixed-order probe sums),
+// ascending slot order (owner-computes object tiles, fixed-shape probe sums),
 // divides, and applies the geometric-mean, phase-aligned joint step of Eq. 6.
 // No floating-point atomics are used anywhere, so every result is bitwise
-// reproducible.
+// reproducible, and every launch strategy runs the same arithmetic.
+//
+// The chain of minibatches is sequential (each one reads the state the
+// previous one wrote), so at the benchmark's sizes the patch stage is bound by
+// latency, not bandwidth: a patch gets up to 1024 threads (16 waves) and each
+// thread loads its probe, object and amplitude values once, up front.
 #include <hip/hip_runtime.h>
-#include <hip/hip_cooperative_groups.h>
 
 #include "device_fft.hpp"
 #include "launch.hpp"
-
-namespace cg = cooperative_groups;
 
 namespace emg {
 
@@ -68,6 +70,12 @@ __device__ __forceinline__ double block_sum(double v, double* red, int tid) {
   return v;
 }
 
+// sum over the four consecutive lanes of a 4 x 4 region (identical in all four)
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __shfl_xor(v, 1);
+  return v + __shfl_xor(v, 2);
+}
+
 __device__ __forceinline__ cx<float> ld(const float2* p, size_t i) {
   float2 v = p[i];
   return cx<float>{v.x, v.y};
@@ -75,43 +83,38 @@ __device__ __forceinline__ cx<float> ld(const float2* p, size_t i) {
 __device__ __forceinline__ void st(float2* p, size_t i, cx<float> v) { p[i] = make_float2(v.re, v.im); }
 
 template <int M>
-struct Tile {
-  static constexpr int NT = Plan<M>::NT;
-  static constexpr int T = NT == 64 ? 16 : (NT == 256 ? 32 : 64);  // object tile side
-  static constexpr int PER = T * T / NT;                             // pixels per thread (4)
+struct Px {
+  static constexpr int BS = Plan<M>::BS, PX = BS * BS, NT = Plan<M>::NT, LS = lds_stride<M>();
+  static constexpr int NSB = PX / 4;  // 2 x 2 sub-blocks per thread block
+  // small blocks keep the thread's probe / object values in registers from the
+  // gather to the numerators; 4 x 4 blocks reload them (register budget)
+  static constexpr bool CACHE = BS == 2;
 };
 
 // ---------------------------------------------------------------------------
-// per-pixel surrogate algebra for one patch (thread owns a 4 x 4 block)
+// per-pixel surrogate algebra for one patch (thread owns a BS x BS block)
+//   qf(e), zf(e), rf(e): probe, object window and revised exit wave at pixel
+//   e = i * BS + j of the block whose top-left pixel is (r0, c0)
 // ---------------------------------------------------------------------------
-template <int M, int L, bool FROM_LDS>
-__device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int2 pk, const float2* Rg,
-                                             const cx<float>* A, float qqmax, float zmax,
-                                             int tid) {
-  constexpr int BW = M / 4, LS = lds_stride<M>();
-  const int bi = tid / BW, bj = tid % BW;
-  const size_t n = (size_t)a.n;
-  auto R_at = [&](int r, int c) -> cx<float> {
-    if constexpr (FROM_LDS) return A[r * LS + c];
-    else return ld(Rg, (size_t)r * M + c);
-  };
+template <int M, int L, class QF, class ZF, class RF>
+__device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int r0, int c0, QF qf, ZF zf,
+                                             RF rf, float qqmax, float zmax) {
+  constexpr int BS = Px<M>::BS, NSB = Px<M>::NSB;
   // pass 1: 2 x 2 sub-block sums of g = conj(Q)(R - Q z), D, u, Q, |Q|^2
-  cx<float> Gs[4], Qs[4];
-  float Ds[4], Us[4], Q2s[4];
+  cx<float> Gs[NSB], Qs[NSB];
+  float Ds[NSB], Us[NSB], Q2s[NSB];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < NSB; ++b) {
     Gs[b] = Qs[b] = cx<float>{0.f, 0.f};
     Ds[b] = Us[b] = Q2s[b] = 0.f;
   }
   if constexpr (L >= 2) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < BS; ++i) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = 4 * bi + i, c = 4 * bj + j, sb = (i >> 1) * 2 + (j >> 1);
-        const cx<float> q = ld(a.probe, (size_t)r * M + c);
-        const cx<float> zz = ld(a.obj, (size_t)(pk.x + r) * n + pk.y + c);
-        const cx<float> R = R_at(r, c);
+      for (int j = 0; j < BS; ++j) {
+        const int e = i * BS + j, sb = (i >> 1) * (BS / 2) + (j >> 1);
+        const cx<float> q = qf(e), zz = zf(e), R = rf(e);
         const float q2 = norm2(q);
         const float u = a.alpha * (qqmax - q2);
         const cx<float> g = cmulc(q, sub(R, mul(q, zz)));
@@ -123,39 +126,45 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int2 pk, 
       }
     }
   }
-  // coarse corrections per 2 x 2 sub-block (block-ratio form of the
-  // restricted coarse solve; three levels recurse once more over the 4 x 4)
-  cx<float> cc[4];
+  // coarse corrections per 2 x 2 sub-block: block-ratio form of the restricted
+  // coarse solve; three levels recurse once more over each 4 x 4 region
+  cx<float> cc[NSB];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) cc[b] = cx<float>{0.f, 0.f};
+  for (int b = 0; b < NSB; ++b) cc[b] = cx<float>{0.f, 0.f};
   if constexpr (L == 2) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < NSB; ++b)
       if (Ds[b] > 0.f) cc[b] = scale(Gs[b], 1.f / Ds[b]);
   } else if constexpr (L == 3) {
+    float wts[NSB];
+#pragma unroll
+    for (int b = 0; b < NSB; ++b) wts[b] = Q2s[b] > 0.f ? norm2(Qs[b]) / (4.f * Q2s[b]) : 0.f;
     cx<float> G2{0.f, 0.f};
     float D2 = 0.f;
+    if constexpr (NSB == 4) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const float w = Q2s[b] > 0.f ? norm2(Qs[b]) / (4.f * Q2s[b]) : 0.f;
-      G2 = add(G2, scale(Gs[b], w));
-      D2 += w * Ds[b];
+      for (int b = 0; b < 4; ++b) {
+        G2 = add(G2, scale(Gs[b], wts[b]));
+        D2 += wts[b] * Ds[b];
+      }
+    } else {
+      G2 = cx<float>{quad_sum(wts[0] * Gs[0].re), quad_sum(wts[0] * Gs[0].im)};
+      D2 = quad_sum(wts[0] * Ds[0]);
     }
     const cx<float> c2 = D2 > 0.f ? scale(G2, 1.f / D2) : cx<float>{0.f, 0.f};
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < NSB; ++b)
       if (Ds[b] > 0.f) cc[b] = scale(add(Gs[b], scale(c2, Us[b])), 1.f / Ds[b]);
   }
   // pass 2: numerators and denominators
   const size_t base = (size_t)s * M * M;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < BS; ++i) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = 4 * bi + i, c = 4 * bj + j, sb = (i >> 1) * 2 + (j >> 1);
-      const cx<float> q = ld(a.probe, (size_t)r * M + c);
-      const cx<float> zz = ld(a.obj, (size_t)(pk.x + r) * n + pk.y + c);
-      const cx<float> R = R_at(r, c);
+    for (int j = 0; j < BS; ++j) {
+      const int e = i * BS + j, sb = (i >> 1) * (BS / 2) + (j >> 1);
+      const int r = r0 + i, c = c0 + j;
+      const cx<float> q = qf(e), zz = zf(e), R = rf(e);
       const float q2 = norm2(q);
       const float u = a.alpha * (qqmax - q2);
       const float D = q2 + u;
@@ -176,129 +185,239 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int2 pk, 
   }
 }
 
-// modulus projection of one thread's 4 x 4 block in transform order:
-// Psi' = a Psi/|Psi| (a where Psi = 0), scaled by 1/m^2; returns sum (|Psi| - a)^2
+// modulus projection of one pixel in transform order: Psi' = a Psi/|Psi|
+// (a where Psi = 0), scaled by 1/m^2; returns (|Psi| - a)^2
 template <int M>
-__device__ __forceinline__ double project_block(cx<float>* A, const float* dk, int tid) {
-  constexpr int BW = M / 4, LS = lds_stride<M>();
-  const int bi = tid / BW, bj = tid % BW;
-  const float inv_m2 = 1.f / float(M * M);
-  double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = 4 * bi + i, c = 4 * bj + j;
-      const cx<float> P = A[r * LS + c];
-      const float amp = sqrtf(fmaxf(dk[r * M + c], 0.f));
-      const float mag = sqrtf(norm2(P));
-      const float diff = mag - amp;
-      acc += (double)diff * (double)diff;
-      const cx<float> o = mag > 0.f ? scale(P, amp / mag) : cx<float>{amp, 0.f};
-      A[r * LS + c] = scale(o, inv_m2);
-    }
-  }
-  return acc;
+__device__ __forceinline__ float project_amp(cx<float>& P, float amp);
+template <int M>
+__device__ __forceinline__ float project_px(cx<float>& P, float dval) {
+  return project_amp<M>(P, sqrtf(fmaxf(dval, 0.f)));
 }
 
-// gather psi = Q . z_k into LDS and return max |Q|^2, max |z_k|^2 (all threads)
 template <int M>
-__device__ __forceinline__ void gather_block(const StepArgs& a, int2 pk, cx<float>* A, float* redf,
-                                             float& qqmax, float& zmax, int tid) {
-  constexpr int BW = M / 4, LS = lds_stride<M>(), NT = Plan<M>::NT;
-  const int bi = tid / BW, bj = tid % BW;
-  const size_t n = (size_t)a.n;
-  float q2m = 0.f, z2m = 0.f;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = 4 * bi + i, c = 4 * bj + j;
-      const cx<float> q = ld(a.probe, (size_t)r * M + c);
-      const cx<float> zz = ld(a.obj, (size_t)(pk.x + r) * n + pk.y + c);
-      q2m = fmaxf(q2m, norm2(q));
-      z2m = fmaxf(z2m, norm2(zz));
-      A[r * LS + c] = mul(q, zz);
-    }
-  }
-  block_max2<NT>(q2m, z2m, redf, tid);
-  qqmax = q2m;
-  zmax = z2m;
-  __syncthreads();
+__device__ __forceinline__ float project_amp(cx<float>& P, float amp) {
+  const float mag = sqrtf(norm2(P));
+  const float diff = mag - amp;
+  const cx<float> o = mag > 0.f ? scale(P, amp / mag) : cx<float>{amp, 0.f};
+  P = scale(o, 1.f / float(M * M));
+  return diff * diff;
 }
 
+// ---------------------------------------------------------------------------
 // the whole patch stage for slot s, LDS-resident
+// ---------------------------------------------------------------------------
 template <int M, int L>
 __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* A,
                                            const cx<float>* tws, float* redf, double* redd,
                                            int tid) {
-  constexpr int NT = Plan<M>::NT;
-  const int k = a.idx[s];
-  const int2 pk = a.pos[k];
-  float qqmax, zmax;
-  gather_block<M>(a, pk, A, redf, qqmax, zmax, tid);
-  fft2_forward<float, M>(A, tws, tid);
-  double acc = project_block<M>(A, a.dperm + (size_t)k * M * M, tid);
+  constexpr int BS = Px<M>::BS, PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
+  const int4 sl = a.slot[s];
+  const int k = sl.x;
+  const int2 pk = make_int2(sl.y, sl.z);
+  const size_t n = (size_t)a.n;
+  const float* dk = a.dperm + (size_t)k * M * M;
+  int r0, c0;
+  block_origin<M>(tid, r0, c0);
+  auto gaddr = [&](int e) { return (size_t)(pk.x + r0 + e / BS) * n + pk.y + c0 + e % BS; };
+  auto paddr = [&](int e) { return (size_t)(r0 + e / BS) * M + c0 + e % BS; };
+  // all global loads of the patch are issued here, before any dependent work
+  cx<float> qc[Px<M>::CACHE ? PX : 1], zc[Px<M>::CACHE ? PX : 1];
+  float amp[PX];
+  float q2m = 0.f, z2m = 0.f;
+#pragma unroll
+  for (int e = 0; e < PX; ++e) amp[e] = dk[paddr(e)];
+#pragma unroll
+  for (int e = 0; e < PX; ++e) amp[e] = sqrtf(fmaxf(amp[e], 0.f));  // consumed before the barrier
+#pragma unroll
+  for (int e = 0; e < PX; ++e) {
+    const cx<float> q = ld(a.probe, paddr(e));
+    const cx<float> zz = ld(a.obj, gaddr(e));
+    if constexpr (Px<M>::CACHE) {
+      qc[e] = q;
+      zc[e] = zz;
+    }
+    q2m = fmaxf(q2m, norm2(q));
+    z2m = fmaxf(z2m, norm2(zz));
+    A[(r0 + e / BS) * LS + c0 + e % BS] = mul(q, zz);
+  }
+  block_max2<NT>(q2m, z2m, redf, tid);
+  const float qqmax = q2m, zmax = z2m;
   __syncthreads();
-  fft2_inverse<float, M>(A, tws, tid);
-  pixel_update<M, L, true>(a, s, pk, nullptr, A, qqmax, zmax, tid);
-  const double tot = block_sum<NT>(acc, redd, tid);
+  fft2_forward<float, M>(A, tws, tid);
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < PX; ++e) acc += (double)project_amp<M>(A[(r0 + e / BS) * LS + c0 + e % BS], amp[e]);
+  const double tot = block_sum<NT>(acc, redd, tid);  // its barriers also order the projection
   if (tid == 0 && a.phi) a.phi[s] = tot / (2.0 * M * M);
   __syncthreads();
+  fft2_inverse<float, M>(A, tws, tid);
+  auto rf = [&](int e) { return A[(r0 + e / BS) * LS + c0 + e % BS]; };
+  if constexpr (Px<M>::CACHE) {
+    pixel_update<M, L>(a, s, r0, c0, [&](int e) { return qc[e]; }, [&](int e) { return zc[e]; }, rf,
+                       qqmax, zmax);
+  } else {
+    pixel_update<M, L>(a, s, r0, c0, [&](int e) { return ld(a.probe, paddr(e)); },
+                       [&](int e) { return ld(a.obj, gaddr(e)); }, rf, qqmax, zmax);
+  }
+  __syncthreads();  // LDS is reused by the next slot of a persistent loop
 }
 
-// finalize work item: an object tile (item < ntiles) or NT probe pixels
-template <int M>
-__device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int ntiles,
-                                              const int2* spos, int tid) {
-  constexpr int NT = Plan<M>::NT, T = Tile<M>::T, PER = Tile<M>::PER;
+// ---------------------------------------------------------------------------
+// finalize: FNT threads per work item
+//   object tile (item < ntiles): T x T pixels, accumulate the numerators of the
+//   overlapping slots in ascending slot order, divide, joint step;
+//   probe units: 64 pixels x 4 slot groups per 256 threads, groups combined in
+//   a fixed order, then the joint step.
+// ---------------------------------------------------------------------------
+template <int FNT>
+struct Fin {
+  static constexpr int T = FNT == 256 ? 32 : (FNT == 1024 ? 64 : 16);
+  static constexpr int PER = T * T / FNT;
+  static constexpr int PROBE_PX = FNT / 4;  // probe pixels per item
+};
+
+struct FinLds {
+  int2 spos[kMaxSlots];
+  int list[kMaxSlots];
+  int nlist;
+  float2 pm[1024];
+  float pe[1024];
+};
+
+template <int M, int FNT>
+__host__ __device__ inline int finalize_items(int n, int* ntiles_out) {
+  constexpr int T = Fin<FNT>::T;
+  const int tpr = (n + T - 1) / T;
+  *ntiles_out = tpr * tpr;
+  return tpr * tpr + (M * M + Fin<FNT>::PROBE_PX - 1) / Fin<FNT>::PROBE_PX;
+}
+
+template <int M, int FNT>
+__device__ __forceinline__ void load_slot_positions(const StepArgs& a, FinLds& L, int tid) {
+  for (int s = tid; s < a.b; s += FNT) L.spos[s] = make_int2(a.slot[s].y, a.slot[s].z);
+}
+
+template <int M, int FNT>
+__device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int ntiles, FinLds& L,
+                                              int tid) {
+  constexpr int T = Fin<FNT>::T, PER = Fin<FNT>::PER;
   const int n = a.n;
   if (item < ntiles) {
     const int tpr = (n + T - 1) / T;
     const int ty = (item / tpr) * T, tx = (item % tpr) * T;
-    cx<float> accn[PER];
-    float accd[PER];
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      accn[e] = cx<float>{0.f, 0.f};
-      accd[e] = 0.f;
+    // wave 0 lists the overlapping slots in ascending order
+    if (tid < 64) {
+      int cnt = 0;
+      for (int s0 = 0; s0 < a.b; s0 += 64) {
+        const int s = s0 + tid;
+        bool ov = false;
+        if (s < a.b) {
+          const int2 p = L.spos[s];
+          ov = !(p.x >= ty + T || p.x + M <= ty || p.y >= tx + T || p.y + M <= tx);
+        }
+        const unsigned long long mask = __ballot(ov);
+        if (ov) L.list[cnt + __popcll(mask & ((1ull << tid) - 1ull))] = s;
+        cnt += __popcll(mask);
+      }
+      if (tid == 0) L.nlist = cnt;
     }
-    for (int s = 0; s < a.b; ++s) {
-      const int2 p = spos[s];
-      if (p.x >= ty + T || p.x + M <= ty || p.y >= tx + T || p.y + M <= tx) continue;
-      const float2* ns = a.numer + (size_t)s * M * M;
+    __syncthreads();
+    const int cnt = L.nlist;
+    if (cnt > 0) {
+      cx<float> accn[PER];
+      float accd[PER];
 #pragma unroll
       for (int e = 0; e < PER; ++e) {
-        const int q = tid + e * NT;
-        const int ry = ty + q / T - p.x, rx = tx + q % T - p.y;
-        if ((unsigned)ry < (unsigned)M && (unsigned)rx < (unsigned)M) {
-          accn[e] = add(accn[e], ld(ns, ry * M + rx));
-          accd[e] += a.Dbuf[ry * M + rx];
+        accn[e] = cx<float>{0.f, 0.f};
+        accd[e] = 0.f;
+      }
+      // four slots per round: every load of the round is issued before any add
+      constexpr int U = 4;
+      for (int i0 = 0; i0 < cnt; i0 += U) {
+        cx<float> vn[U][PER];
+        float vd[U][PER];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u;
+          const int s = i < cnt ? L.list[i] : 0;
+          const int2 p = L.spos[s];
+          const float2* ns = a.numer + (size_t)s * M * M;
+#pragma unroll
+          for (int e = 0; e < PER; ++e) {
+            const int q = tid + e * FNT;
+            const int ry = ty + q / T - p.x, rx = tx + q % T - p.y;
+            const bool in = i < cnt && (unsigned)ry < (unsigned)M && (unsigned)rx < (unsigned)M;
+            vn[u][e] = in ? ld(ns, ry * M + rx) : cx<float>{0.f, 0.f};
+            vd[u][e] = in ? a.Dbuf[ry * M + rx] : 0.f;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+          for (int e = 0; e < PER; ++e) {
+            if (i0 + u < cnt) {
+              accn[e] = add(accn[e], vn[u][e]);
+              accd[e] += vd[u][e];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int q = tid + e * FNT;
+        const int y = ty + q / T, x = tx + q % T;
+        if (accd[e] > 0.f && y < n && x < n) {
+          const size_t o = (size_t)y * n + x;
+          const cx<float> z = ld(a.obj, o);
+          st(a.obj, o, aligned_sqrt(z, scale(accn[e], 1.f / accd[e])));
         }
       }
     }
+    __syncthreads();  // the slot list is rewritten by the next tile
+  } else {
+    const int lt = tid & 255, unit = tid >> 8;
+    const int g = lt >> 6;
+    const int r = (item - ntiles) * Fin<FNT>::PROBE_PX + unit * 64 + (lt & 63);
+    const bool live = a.update_probe && r < M * M;
+    const int per = (a.b + 3) / 4;
+    const int s_lo = g * per, s_hi = min(a.b, s_lo + per);
+    cx<float> mac{0.f, 0.f};
+    float eac = 0.f;
+    if (live) {
+      // eight slots per round: the round's loads are all issued before its adds
+      constexpr int U = 8;
+      for (int s0 = s_lo; s0 < s_hi; s0 += U) {
+        cx<float> vm[U];
+        float ve[U];
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int q = tid + e * NT;
-      const int y = ty + q / T, x = tx + q % T;
-      if (accd[e] > 0.f && y < n && x < n) {
-        const size_t o = (size_t)y * n + x;
-        const cx<float> z = ld(a.obj, o);
-        st(a.obj, o, aligned_sqrt(z, scale(accn[e], 1.f / accd[e])));
+        for (int u = 0; u < U; ++u) {
+          const bool in = s0 + u < s_hi;
+          const size_t o = (size_t)(in ? s0 + u : s_lo) * M * M + r;
+          vm[u] = in ? ld(a.pnum, o) : cx<float>{0.f, 0.f};
+          ve[u] = in ? a.pden[o] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (s0 + u < s_hi) {
+            mac = add(mac, vm[u]);
+            eac += ve[u];
+          }
+        }
       }
     }
-  } else {
-    const int r = (item - ntiles) * NT + tid;
-    if (a.update_probe && r < M * M) {
-      cx<float> mac{0.f, 0.f};
-      float eac = 0.f;
-      for (int s = 0; s < a.b; ++s) {
-        mac = add(mac, ld(a.pnum, (size_t)s * M * M + r));
-        eac += a.pden[(size_t)s * M * M + r];
-      }
-      if (eac > 0.f) {
+    L.pm[tid] = make_float2(mac.re, mac.im);
+    L.pe[tid] = eac;
+    __syncthreads();
+    if (g == 0 && live) {
+      const int b0 = unit * 256 + (lt & 63);
+      const cx<float> m01 = add(ld(L.pm, b0), ld(L.pm, b0 + 64));
+      const cx<float> m23 = add(ld(L.pm, b0 + 128), ld(L.pm, b0 + 192));
+      const float e01 = L.pe[b0] + L.pe[b0 + 64], e23 = L.pe[b0 + 128] + L.pe[b0 + 192];
+      const cx<float> mt = add(m01, m23);
+      const float et = e01 + e23;
+      if (et > 0.f) {
         const cx<float> q = ld(a.probe, r);
-        st(a.probe, r, aligned_sqrt(q, scale(mac, 1.f / eac)));
+        st(a.probe, r, aligned_sqrt(q, scale(mt, 1.f / et)));
       }
     }
     if (item == ntiles && tid == 0 && a.sampled) {
@@ -306,15 +425,8 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
       for (int s = 0; s < a.b; ++s) t += a.phi[s];
       *a.sampled += t;
     }
+    __syncthreads();
   }
-}
-
-template <int M>
-__host__ __device__ inline int finalize_items(int n, int* ntiles_out) {
-  constexpr int T = Tile<M>::T, NT = Plan<M>::NT;
-  const int tpr = (n + T - 1) / T;
-  *ntiles_out = tpr * tpr;
-  return tpr * tpr + (M * M + NT - 1) / NT;
 }
 
 // ---------------------------------------------------------------------------
@@ -337,41 +449,73 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_patch_step(StepArgs a) {
   patch_step<M, L>(a, blockIdx.x, A, tws, redf, redd, tid);
 }
 
+constexpr int kFinNT = 256;
+
 template <int M>
-__global__ __launch_bounds__(Plan<M>::NT) void k_finalize(StepArgs a, int ntiles) {
-  __shared__ int2 spos[kMaxSlots];
+__global__ __launch_bounds__(kFinNT) void k_finalize(StepArgs a, int ntiles) {
+  __shared__ FinLds L;
   const int tid = threadIdx.x;
-  for (int s = tid; s < a.b; s += Plan<M>::NT) spos[s] = a.pos[a.idx[s]];
+  load_slot_positions<M, kFinNT>(a, L, tid);
   __syncthreads();
-  finalize_item<M>(a, blockIdx.x, ntiles, spos, tid);
+  finalize_item<M, kFinNT>(a, blockIdx.x, ntiles, L, tid);
+}
+
+// Grid-wide barrier for the persistent kernel (all workgroups co-resident by
+// cooperative launch).  Each wave waits until its own global stores have
+// reached L2; then one lane per workgroup releases at agent scope (L2
+// write-back, so other XCDs see the data), arrives on a monotonic counter,
+// waits for the target and acquires (stale lines dropped from this CU's L1 and
+// this XCD's L2) before the workgroup proceeds.  A bounded spin turns a lost
+// arrival into an error flag instead of a hang.
+__device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned target, int* err) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(4);
+      if (++spins > (1u << 25)) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
 }
 
 // persistent epoch: every minibatch of a sweep in one cooperative launch
 template <int M, int L>
 __global__ __launch_bounds__(Plan<M>::NT) void k_epoch_persistent(StepArgs a, int n_pos, int B,
-                                                                  int ntiles, int nitems) {
+                                                                  int ntiles, int nitems,
+                                                                  unsigned* bar, unsigned bar_base,
+                                                                  int* err) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ float redf[32];
   __shared__ double redd[16];
-  __shared__ int2 spos[kMaxSlots];
+  __shared__ FinLds FL;
   constexpr int NT = Plan<M>::NT;
-  cg::grid_group grid = cg::this_grid();
   const int tid = threadIdx.x;
   stage_twiddles<M>(a.tw, tws, tid);
   __syncthreads();
-  const int* perm = a.idx;
+  const int4* slots = a.slot;
+  unsigned target = bar_base;
   for (int start = 0; start < n_pos; start += B) {
     StepArgs x = a;
-    x.idx = perm + start;
+    x.slot = slots + start;
     x.b = min(B, n_pos - start);
     for (int s = blockIdx.x; s < x.b; s += gridDim.x) patch_step<M, L>(x, s, A, tws, redf, redd, tid);
-    grid.sync();
-    for (int s = tid; s < x.b; s += NT) spos[s] = x.pos[x.idx[s]];
+    target += gridDim.x;
+    grid_barrier(bar, target, err);
+    load_slot_positions<M, NT>(x, FL, tid);
     __syncthreads();
     for (int item = blockIdx.x; item < nitems; item += gridDim.x)
-      finalize_item<M>(x, item, ntiles, spos, tid);
-    grid.sync();
+      finalize_item<M, NT>(x, item, ntiles, FL, tid);
+    target += gridDim.x;
+    grid_barrier(bar, target, err);
   }
 }
 
@@ -391,19 +535,20 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_probe_prep(StepArgs a) {
 template <int M>
 __global__ __launch_bounds__(Plan<M>::NT) void k_gather(StepArgs a) {
   __shared__ float redf[32];
-  constexpr int BW = M / 4;
+  constexpr int BS = Px<M>::BS, PX = Px<M>::PX;
   const int tid = threadIdx.x, s = blockIdx.x;
-  const int2 pk = a.pos[a.idx[s]];
-  const int bi = tid / BW, bj = tid % BW;
+  const int2 pk = make_int2(a.slot[s].y, a.slot[s].z);
+  int r0, c0;
+  block_origin<M>(tid, r0, c0);
   float z2m = 0.f, dummy = 0.f;
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      const int r = 4 * bi + i, c = 4 * bj + j;
-      const cx<float> q = ld(a.probe, (size_t)r * M + c);
-      const cx<float> zz = ld(a.obj, (size_t)(pk.x + r) * a.n + pk.y + c);
-      z2m = fmaxf(z2m, norm2(zz));
-      st(a.stack, (size_t)s * M * M + r * M + c, mul(q, zz));
-    }
+#pragma unroll
+  for (int e = 0; e < PX; ++e) {
+    const int r = r0 + e / BS, c = c0 + e % BS;
+    const cx<float> q = ld(a.probe, (size_t)r * M + c);
+    const cx<float> zz = ld(a.obj, (size_t)(pk.x + r) * a.n + pk.y + c);
+    z2m = fmaxf(z2m, norm2(zz));
+    st(a.stack, (size_t)s * M * M + r * M + c, mul(q, zz));
+  }
   block_max2<Plan<M>::NT>(z2m, dummy, redf, tid);
   if (tid == 0) a.zmax[s] = z2m;
 }
@@ -425,26 +570,39 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_fft(StepArgs a) {
 
 template <int M>
 __global__ __launch_bounds__(Plan<M>::NT) void k_project(StepArgs a) {
-  __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ double redd[16];
-  constexpr int NT = Plan<M>::NT, LS = lds_stride<M>();
+  constexpr int BS = Px<M>::BS, PX = Px<M>::PX, NT = Px<M>::NT;
   const int tid = threadIdx.x, s = blockIdx.x;
   float2* X = a.stack + (size_t)s * M * M;
-  for (int e = tid; e < M * M; e += NT) A[(e / M) * LS + e % M] = ld(X, e);
-  __syncthreads();
-  const double acc = project_block<M>(A, a.dperm + (size_t)a.idx[s] * M * M, tid);
-  __syncthreads();
-  for (int e = tid; e < M * M; e += NT) st(X, e, A[(e / M) * LS + e % M]);
+  const float* dk = a.dperm + (size_t)a.slot[s].x * M * M;
+  int r0, c0;
+  block_origin<M>(tid, r0, c0);
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < PX; ++e) {
+    const size_t o = (size_t)(r0 + e / BS) * M + c0 + e % BS;
+    cx<float> P = ld(X, o);
+    acc += (double)project_px<M>(P, dk[o]);
+    st(X, o, P);
+  }
   const double tot = block_sum<NT>(acc, redd, tid);
   if (tid == 0 && a.phi) a.phi[s] = tot / (2.0 * M * M);
 }
 
 template <int M, int L>
 __global__ __launch_bounds__(Plan<M>::NT) void k_numerators(StepArgs a) {
-  const int s = blockIdx.x;
-  const int2 pk = a.pos[a.idx[s]];
-  pixel_update<M, L, false>(a, s, pk, a.stack + (size_t)s * M * M, nullptr, a.qqmax[0], a.zmax[s],
-                            threadIdx.x);
+  constexpr int BS = Px<M>::BS;
+  const int tid = threadIdx.x, s = blockIdx.x;
+  const int2 pk = make_int2(a.slot[s].y, a.slot[s].z);
+  const size_t n = (size_t)a.n;
+  const float2* Rg = a.stack + (size_t)s * M * M;
+  int r0, c0;
+  block_origin<M>(tid, r0, c0);
+  auto paddr = [&](int e) { return (size_t)(r0 + e / BS) * M + c0 + e % BS; };
+  auto gaddr = [&](int e) { return (size_t)(pk.x + r0 + e / BS) * n + pk.y + c0 + e % BS; };
+  pixel_update<M, L>(a, s, r0, c0, [&](int e) { return ld(a.probe, paddr(e)); },
+                     [&](int e) { return ld(a.obj, gaddr(e)); },
+                     [&](int e) { return ld(Rg, paddr(e)); }, a.qqmax[0], a.zmax[s]);
 }
 
 // ---------------------------------------------------------------------------
@@ -457,19 +615,26 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_misfit(const float2* obj, int n
                                                         double* phi_all) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
-  __shared__ float redf[32];
   __shared__ double redd[16];
-  constexpr int NT = Plan<M>::NT;
+  constexpr int BS = Px<M>::BS, PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
   const int tid = threadIdx.x, k = blockIdx.x;
+  const int2 pk = pos[k];
+  const float* dk = dperm + (size_t)k * M * M;
+  int r0, c0;
+  block_origin<M>(tid, r0, c0);
   stage_twiddles<M>(tw, tws, tid);
-  StepArgs a{};
-  a.obj = const_cast<float2*>(obj);
-  a.n = n;
-  a.probe = const_cast<float2*>(probe);
-  float qq, zm;
-  gather_block<M>(a, pos[k], A, redf, qq, zm, tid);
+  float dv[PX];
+#pragma unroll
+  for (int e = 0; e < PX; ++e) {
+    const int r = r0 + e / BS, c = c0 + e % BS;
+    dv[e] = dk[r * M + c];
+    A[r * LS + c] = mul(ld(probe, (size_t)r * M + c), ld(obj, (size_t)(pk.x + r) * n + pk.y + c));
+  }
+  __syncthreads();
   fft2_forward<float, M>(A, tws, tid);
-  const double acc = project_block<M>(A, dperm + (size_t)k * M * M, tid);
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < PX; ++e) acc += (double)project_px<M>(A[(r0 + e / BS) * LS + c0 + e % BS], dv[e]);
   const double tot = block_sum<NT>(acc, redd, tid);
   if (tid == 0) phi_all[k] = tot / (2.0 * M * M);
 }
@@ -488,19 +653,18 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_patch(GradArgs g, int k0) 
   __shared__ cx<T> A[M * lds_stride<M>()];
   __shared__ cx<T> tws[M];
   __shared__ double redd[16];
-  constexpr int NT = Plan<M>::NT, BW = M / 4, LS = lds_stride<M>();
+  constexpr int BS = Px<M>::BS, PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
   const int tid = threadIdx.x, s = blockIdx.x, k = k0 + s;
-  const int bi = tid / BW, bj = tid % BW;
   const int2 pk = g.pos[k];
   const size_t n = (size_t)g.n;
+  int r0, c0;
+  block_origin<M>(tid, r0, c0);
   for (int j = tid; j < M; j += NT) tws[j] = ldT<T>(g.tw, j);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = 4 * bi + i, c = 4 * bj + j;
-      A[r * LS + c] = mul(ldT<T>(g.probe, (size_t)r * M + c), ldT<T>(g.obj, (pk.x + r) * n + pk.y + c));
-    }
+  for (int e = 0; e < PX; ++e) {
+    const int r = r0 + e / BS, c = c0 + e % BS;
+    A[r * LS + c] = mul(ldT<T>(g.probe, (size_t)r * M + c), ldT<T>(g.obj, (pk.x + r) * n + pk.y + c));
+  }
   __syncthreads();
   fft2_forward<T, M>(A, tws, tid);
   // residual in Fourier space: Psi - Psi' = (|Psi| - a) Psi/|Psi|, or -a where Psi = 0
@@ -508,43 +672,38 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_patch(GradArgs g, int k0) 
   const T inv_m2 = T(1) / T(M * M);
   double acc = 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = 4 * bi + i, c = 4 * bj + j;
-      const cx<T> P = A[r * LS + c];
-      const T amp = sqrt(fmax(T(dk[r * M + c]), T(0)));
-      const T mag = sqrt(norm2(P));
-      const T diff = mag - amp;
-      acc += (double)diff * (double)diff;
-      const cx<T> E = mag > T(0) ? scale(P, diff / mag) : cx<T>{-amp, T(0)};
-      A[r * LS + c] = scale(E, inv_m2);
-    }
+  for (int e = 0; e < PX; ++e) {
+    const int r = r0 + e / BS, c = c0 + e % BS;
+    const cx<T> P = A[r * LS + c];
+    const T amp = sqrt(fmax(T(dk[r * M + c]), T(0)));
+    const T mag = sqrt(norm2(P));
+    const T diff = mag - amp;
+    acc += (double)diff * (double)diff;
+    const cx<T> E = mag > T(0) ? scale(P, diff / mag) : cx<T>{-amp, T(0)};
+    A[r * LS + c] = scale(E, inv_m2);
+  }
   __syncthreads();
   fft2_inverse<T, M>(A, tws, tid);
   const size_t base = (size_t)s * M * M;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = 4 * bi + i, c = 4 * bj + j;
-      const cx<T> e = A[r * LS + c];
-      const cx<T> q = ldT<T>(g.probe, (size_t)r * M + c);
-      const cx<T> zz = ldT<T>(g.obj, (pk.x + r) * n + pk.y + c);
-      stT<T>(g.gz_slots, base + r * M + c, cmulc(q, e));
-      stT<T>(g.gq_slots, base + r * M + c, cmulc(zz, e));
-    }
+  for (int e = 0; e < PX; ++e) {
+    const int r = r0 + e / BS, c = c0 + e % BS;
+    const cx<T> ev = A[r * LS + c];
+    const cx<T> q = ldT<T>(g.probe, (size_t)r * M + c);
+    const cx<T> zz = ldT<T>(g.obj, (pk.x + r) * n + pk.y + c);
+    stT<T>(g.gz_slots, base + r * M + c, cmulc(q, ev));
+    stT<T>(g.gq_slots, base + r * M + c, cmulc(zz, ev));
+  }
   const double tot = block_sum<NT>(acc, redd, tid);
   if (tid == 0) g.phi_all[k] = tot / (2.0 * M * M);
 }
 
 template <typename T, int M>
-__global__ __launch_bounds__(Plan<M>::NT) void k_grad_scatter(GradArgs g, int k0, int cnt,
-                                                              int first) {
+__global__ __launch_bounds__(256) void k_grad_scatter(GradArgs g, int k0, int cnt, int first) {
   __shared__ int2 spos[kMaxSlots];
-  constexpr int NT = Plan<M>::NT, TS = Tile<M>::T, PER = Tile<M>::PER;
+  constexpr int TS = 32, PER = 4;
   const int tid = threadIdx.x, n = g.n;
-  for (int s = tid; s < cnt; s += NT) spos[s] = g.pos[k0 + s];
+  for (int s = tid; s < cnt; s += 256) spos[s] = g.pos[k0 + s];
   __syncthreads();
   const int tpr = (n + TS - 1) / TS;
   const int ty = (blockIdx.x / tpr) * TS, tx = (blockIdx.x % tpr) * TS;
@@ -556,7 +715,7 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_scatter(GradArgs g, int k0
     if (p.x >= ty + TS || p.x + M <= ty || p.y >= tx + TS || p.y + M <= tx) continue;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-      const int q = tid + e * NT;
+      const int q = tid + e * 256;
       const int ry = ty + q / TS - p.x, rx = tx + q % TS - p.y;
       if ((unsigned)ry < (unsigned)M && (unsigned)rx < (unsigned)M)
         acc[e] = add(acc[e], ldT<T>(g.gz_slots, (size_t)s * M * M + ry * M + rx));
@@ -564,7 +723,7 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_scatter(GradArgs g, int k0
   }
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
-    const int q = tid + e * NT;
+    const int q = tid + e * 256;
     const int y = ty + q / TS, x = tx + q % TS;
     if (y < n && x < n) {
       const size_t o = (size_t)y * n + x;
@@ -586,44 +745,41 @@ __global__ __launch_bounds__(256) void k_grad_probe(GradArgs g, int cnt, int fir
 // init helpers
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ __launch_bounds__(Plan<M>::NT) void k_layout(const float* d, float* dperm,
-                                                        double* sums, int* bad) {
+__global__ __launch_bounds__(256) void k_layout(const float* d, float* dperm, double* sums,
+                                                int* bad) {
   __shared__ double redd[16];
-  constexpr int NT = Plan<M>::NT;
   const int tid = threadIdx.x, k = blockIdx.x;
   const float* src = d + (size_t)k * M * M;
   float* dst = dperm + (size_t)k * M * M;
   double acc = 0.0;
   int nonfinite = 0;
-  for (int e = tid; e < M * M; e += NT) {
+  for (int e = tid; e < M * M; e += 256) {
     const float v = src[freq_of_pos<M>(e / M) * M + freq_of_pos<M>(e % M)];
     dst[e] = v;
     nonfinite |= !isfinite(v);
     acc += (double)v;
   }
   if (nonfinite) atomicOr(bad, 1);
-  const double tot = block_sum<NT>(acc, redd, tid);
+  const double tot = block_sum<256>(acc, redd, tid);
   if (tid == 0) sums[k] = tot;
 }
 
 template <int M>
-__global__ __launch_bounds__(Plan<M>::NT) void k_normalize(float2* probe, double dp_avg,
-                                                           int* zero_flag) {
+__global__ __launch_bounds__(256) void k_normalize(float2* probe, double dp_avg, int* zero_flag) {
   __shared__ double redd[16];
-  constexpr int NT = Plan<M>::NT;
   const int tid = threadIdx.x;
   double acc = 0.0;
-  for (int r = tid; r < M * M; r += NT) {
+  for (int r = tid; r < M * M; r += 256) {
     const float2 v = probe[r];
     acc += (double)v.x * v.x + (double)v.y * v.y;
   }
-  const double tot = block_sum<NT>(acc, redd, tid);
+  const double tot = block_sum<256>(acc, redd, tid);
   if (tot == 0.0) {
     if (tid == 0) zero_flag[0] = 1;
     return;
   }
   const float sc = (float)(dp_avg / sqrt(tot));
-  for (int r = tid; r < M * M; r += NT) {
+  for (int r = tid; r < M * M; r += 256) {
     const float2 v = probe[r];
     probe[r] = make_float2(v.x * sc, v.y * sc);
   }
@@ -640,6 +796,17 @@ __global__ __launch_bounds__(256) void k_sum_doubles(const double* in, int count
 __global__ __launch_bounds__(256) void k_zero_doubles(double* p, int count) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < count) p[i] = 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_zero_u32(unsigned* p) { p[threadIdx.x] = 0u; }
+
+__global__ __launch_bounds__(256) void k_slot_info(const int* idx, const int2* pos, int n_pos,
+                                                   int4* slot, int count) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= count) return;
+  const int k = min(max(idx[j], 0), n_pos - 1);
+  const int2 p = pos[k];
+  slot[j] = make_int4(k, p.x, p.y, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -679,8 +846,8 @@ hipError_t launch_patch_step(int m, int L, const StepArgs& a, hipStream_t s) {
 template <int M>
 static hipError_t finalize_l(const StepArgs& a, hipStream_t s) {
   int ntiles;
-  const int items = finalize_items<M>(a.n, &ntiles);
-  hipLaunchKernelGGL(k_finalize<M>, dim3(items), dim3(Plan<M>::NT), 0, s, a, ntiles);
+  const int items = finalize_items<M, kFinNT>(a.n, &ntiles);
+  hipLaunchKernelGGL(k_finalize<M>, dim3(items), dim3(kFinNT), 0, s, a, ntiles);
   return hipGetLastError();
 }
 hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s) {
@@ -716,19 +883,34 @@ hipError_t persistent_grid_size(int m, int L, int num_cus, int* grid) {
 }
 
 template <int M, int L>
-static hipError_t persistent_l(const StepArgs& a, int n_pos, int B, int grid, hipStream_t s) {
+static hipError_t persistent_l(const StepArgs& a, int n_pos, int B, int grid, unsigned* bar,
+                               unsigned bar_base, int* err, int* used_grid, hipStream_t s) {
   int ntiles;
-  int nitems = finalize_items<M>(a.n, &ntiles);
+  int nitems = finalize_items<M, Plan<M>::NT>(a.n, &ntiles);
   StepArgs aa = a;
-  void* args[] = {&aa, &n_pos, &B, &ntiles, &nitems};
   const int want = max(min(B, n_pos), nitems);
-  const int g = max(1, min(grid, want));
+  int g = max(1, min(grid, want));
+  *used_grid = g;
+  void* args[] = {&aa, &n_pos, &B, &ntiles, &nitems, &bar, &bar_base, &err};
   return hipLaunchCooperativeKernel((const void*)k_epoch_persistent<M, L>, dim3(g),
                                     dim3(Plan<M>::NT), args, 0, s);
 }
 hipError_t launch_persistent_epoch(int m, int L, const StepArgs& a, int n_pos, int minibatch,
-                                   int grid, hipStream_t s) {
-  EMG_DISPATCH_ML(m, L, persistent_l, a, n_pos, minibatch, grid, s);
+                                   int grid, unsigned* bar, unsigned bar_base, int* err,
+                                   int* used_grid, hipStream_t s) {
+  EMG_DISPATCH_ML(m, L, persistent_l, a, n_pos, minibatch, grid, bar, bar_base, err, used_grid, s);
+}
+
+hipError_t launch_slot_info(const int* idx, const int2* pos, int n_pos, int4* slot, int count,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_slot_info, dim3((count + 255) / 256), dim3(256), 0, s, idx, pos, n_pos, slot,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, p);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_doubles(double* p, int count, hipStream_t s) {
@@ -744,7 +926,7 @@ hipError_t launch_sum_doubles(const double* in, int count, double* out, hipStrea
 template <int M>
 static hipError_t layout_l(const float* d, float* dperm, int n_pos, double* sums, int* bad,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_layout<M>, dim3(n_pos), dim3(Plan<M>::NT), 0, s, d, dperm, sums, bad);
+  hipLaunchKernelGGL(k_layout<M>, dim3(n_pos), dim3(256), 0, s, d, dperm, sums, bad);
   return hipGetLastError();
 }
 hipError_t launch_layout_intensities(int m, const float* d, float* dperm, int n_pos,
@@ -754,7 +936,7 @@ hipError_t launch_layout_intensities(int m, const float* d, float* dperm, int n_
 
 template <int M>
 static hipError_t normalize_l(float2* probe, double dp_avg, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize<M>, dim3(1), dim3(Plan<M>::NT), 0, s, probe, dp_avg, flag);
+  hipLaunchKernelGGL(k_normalize<M>, dim3(1), dim3(256), 0, s, probe, dp_avg, flag);
   return hipGetLastError();
 }
 hipError_t launch_normalize_probe(int m, float2* probe, double dp_avg, int* zero_flag,
@@ -778,13 +960,13 @@ hipError_t launch_misfit_terms(int m, const float2* obj, int n, const float2* pr
 
 template <typename T, int M>
 static hipError_t grad_t(const GradArgs& g, hipStream_t s) {
-  constexpr int NT = Plan<M>::NT, TS = Tile<M>::T;
+  constexpr int NT = Plan<M>::NT, TS = 32;
   const int tpr = (g.n + TS - 1) / TS;
   for (int k0 = 0; k0 < g.n_pos; k0 += g.chunk) {
     const int cnt = min(g.chunk, g.n_pos - k0);
     const int first = k0 == 0;
     hipLaunchKernelGGL((k_grad_patch<T, M>), dim3(cnt), dim3(NT), 0, s, g, k0);
-    hipLaunchKernelGGL((k_grad_scatter<T, M>), dim3(tpr * tpr), dim3(NT), 0, s, g, k0, cnt, first);
+    hipLaunchKernelGGL((k_grad_scatter<T, M>), dim3(tpr * tpr), dim3(256), 0, s, g, k0, cnt, first);
     hipLaunchKernelGGL((k_grad_probe<T, M>), dim3((M * M + 255) / 256), dim3(256), 0, s, g, cnt,
                        first);
     hipError_t e = hipGetLastError();

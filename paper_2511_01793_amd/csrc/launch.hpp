@@ -16,7 +16,7 @@ struct StepArgs {
   // measured data in transform order, scan windows
   const float* dperm;  // N x m x m
   const int2* pos;     // N (row, col)
-  const int* idx;      // b slot -> scan index
+  const int4* slot;    // b entries: (scan index k, window row, window col, 0)
   int b;
   float alpha, alpha_z;
   int update_probe;
@@ -42,10 +42,20 @@ hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s);
 hipError_t launch_plain_step(int m, int L, const StepArgs& a, hipStream_t s);
 
 // Persistent epoch: one cooperative launch runs every minibatch of a sweep.
-// a.idx must point at the full permutation (N entries); a.b is ignored.
+// a.slot must point at the slot list of the whole sweep (N entries); a.b is ignored.
+// `bar` is a device counter that only grows: the kernel's barriers wait for
+// bar_base + (i + 1) * grid arrivals; `err` is set if a barrier wait gives up.
 hipError_t persistent_grid_size(int m, int L, int num_cus, int* grid);
 hipError_t launch_persistent_epoch(int m, int L, const StepArgs& a, int n_pos, int minibatch,
-                                   int grid, hipStream_t s);
+                                   int grid, unsigned* bar, unsigned bar_base, int* err,
+                                   int* used_grid, hipStream_t s);
+// zero 64 consecutive unsigned counters
+hipError_t launch_zero_u32(unsigned* p, hipStream_t s);
+
+// slot[j] = (idx[j], pos[idx[j]]) for j < count; indices outside [0, n_pos)
+// are clamped so that no access leaves the buffers (the result is then undefined)
+hipError_t launch_slot_info(const int* idx, const int2* pos, int n_pos, int4* slot, int count,
+                            hipStream_t s);
 
 // zero `count` doubles
 hipError_t launch_zero_doubles(double* p, int count, hipStream_t s);
