@@ -80,7 +80,7 @@ def time_to_target(rec, obj, probe, target, max_epochs):
     return None, max_epochs, float(phi.item())
 
 
-def cpu_baseline(p, budget_s=15.0):
+def cpu_baseline(p, budget_s=10.0):
     """FP64 oracle on a bounded sample: consecutive minibatches of the first epoch."""
     from oracle import emagpie_oracle as O
     a = O.amplitudes(p.intensities)
@@ -90,7 +90,7 @@ def cpu_baseline(p, budget_s=15.0):
     done = 0
     t0 = time.perf_counter()
     nb = 0
-    while time.perf_counter() - t0 < budget_s and done < p.n_pos * 4:
+    while time.perf_counter() - t0 < budget_s and done < p.n_pos * 40:
         s = (nb * p.minibatch) % p.n_pos
         idx = perm[s:s + p.minibatch]
         q, z, _ = O.step_minibatch(q, z, p.positions, a, idx, alpha=p.alpha, levels=p.levels)

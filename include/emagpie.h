@@ -166,11 +166,12 @@ emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* pr
 emagpie_status emagpie_permutation(uint64_t seed, int64_t epoch, int32_t n, int32_t* out_host);
 
 /*
- * Kernel timing for benchmarks.  While enabled, HIP events are recorded on the
- * caller's stream around every patch-stage launch group and every finalize
- * launch of the plain and fused paths, and around every persistent-epoch
- * launch (captured-graph replays are not instrumented).  Host only; events are
- * library-owned host objects.
+ * Kernel timing for benchmarks.  While enabled, the fused path's patch-stage
+ * and finalize kernels are launched with HIP events that the runtime
+ * timestamps at the kernel's own start and end; the plain path's six
+ * patch-stage kernels and every persistent-epoch launch are bracketed by
+ * events recorded on the caller's stream.  Captured-graph replays are not
+ * instrumented.  Host only; events are library-owned host objects.
  */
 emagpie_status emagpie_profile_enable(emagpie_ctx ctx, int32_t enable);
 

@@ -181,15 +181,17 @@ emg::StepArgs base_args(emagpie_ctx c, void* obj, void* probe) {
   return a;
 }
 
-// record one event of a (start, stop) pair for timing category `cat`
-emagpie_status mark(emagpie_ctx c, int cat, bool instrument, hipStream_t s) {
+// a (start, stop) event pair for timing category `cat`, or nulls when not timing
+emagpie_status take_pair(emagpie_ctx c, int cat, bool instrument, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
   if (!c->profile || !instrument) return EMAGPIE_OK;
-  if (c->ev_used[cat] == c->ev[cat].size()) {
+  while (c->ev[cat].size() < c->ev_used[cat] + 2) {
     hipEvent_t e;
     EMG_HIP(hipEventCreate(&e));
     c->ev[cat].push_back(e);
   }
-  EMG_HIP(hipEventRecord(c->ev[cat][c->ev_used[cat]++], s));
+  *e0 = c->ev[cat][c->ev_used[cat]++];
+  *e1 = c->ev[cat][c->ev_used[cat]++];
   return EMAGPIE_OK;
 }
 
@@ -203,16 +205,18 @@ emagpie_status mark(emagpie_ctx c, int cat, bool instrument, hipStream_t s) {
 emagpie_status enqueue_minibatch(emagpie_ctx c, const emg::StepArgs& a, bool plain, hipStream_t s,
                                  bool instrument = true) {
   const int m = c->cfg.m, L = c->cfg.levels;
-  EMG_OK(mark(c, 0, instrument, s));
+  hipEvent_t e0, e1;
+  EMG_OK(take_pair(c, 0, instrument, &e0, &e1));
   if (plain) {
+    // six kernels: the pair brackets the group on the stream
+    if (e0) EMG_HIP(hipEventRecord(e0, s));
     EMG_HIP(emg::launch_plain_step(m, L, a, s));
+    if (e1) EMG_HIP(hipEventRecord(e1, s));
   } else {
-    EMG_HIP(emg::launch_patch_step(m, L, a, s));
+    EMG_HIP(emg::launch_patch_step(m, L, a, s, e0, e1));
   }
-  EMG_OK(mark(c, 0, instrument, s));
-  EMG_OK(mark(c, 1, instrument, s));
-  EMG_HIP(emg::launch_finalize(m, a, s));
-  EMG_OK(mark(c, 1, instrument, s));
+  EMG_OK(take_pair(c, 1, instrument, &e0, &e1));
+  EMG_HIP(emg::launch_finalize(m, a, s, e0, e1));
   return EMAGPIE_OK;
 }
 
@@ -514,11 +518,13 @@ emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, in
         ctx->bar_ready = true;
       }
       int used = 0;
-      EMG_OK(mark(ctx, 2, true, s));
+      hipEvent_t e0, e1;
+      EMG_OK(take_pair(ctx, 2, true, &e0, &e1));
+      if (e0) EMG_HIP(hipEventRecord(e0, s));
       EMG_HIP(emg::launch_persistent_epoch(ctx->cfg.m, ctx->cfg.levels, a, N, ctx->cfg.minibatch,
                                            ctx->persist_grid, ctx->bar, ctx->bar_base,
                                            ctx->scal_i + 2, &used, s));
-      EMG_OK(mark(ctx, 2, true, s));
+      if (e1) EMG_HIP(hipEventRecord(e1, s));
       const unsigned nbatch = (unsigned)((N + ctx->cfg.minibatch - 1) / ctx->cfg.minibatch);
       ctx->bar_base += 2u * nbatch * (unsigned)used;
       return EMAGPIE_OK;

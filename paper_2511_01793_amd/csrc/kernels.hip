@@ -17,6 +17,7 @@
 // previous one wrote), so at the benchmark's sizes the patch stage is bound by
 // latency, not bandwidth: a patch gets up to 1024 threads (16 waves) and each
 // thread loads its probe, object and amplitude values once, up front.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device_fft.hpp"
@@ -25,55 +26,100 @@
 namespace emg {
 
 // ---------------------------------------------------------------------------
-// block reductions (wave64 butterflies, then a fixed-order pass over waves)
+// reductions.  Within a wave: DPP lane permutes (quad swaps, then the half-row
+// and row mirrors) leave every lane of a 16-lane row with its row's total; the
+// four row totals are combined in a fixed order through readlane.  Across the
+// waves of a block: one value per wave in LDS, combined in wave order.  All
+// orders are fixed, so every sum is bitwise reproducible.
 // ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E, kDppRowHalfMirror = 0x141,
+              kDppRowMirror = 0x140;
+
+__device__ __forceinline__ float wave_max(float v) {
+  v = fmaxf(v, dpp_f<kDppQuadXor1>(v));
+  v = fmaxf(v, dpp_f<kDppQuadXor2>(v));
+  v = fmaxf(v, dpp_f<kDppRowHalfMirror>(v));
+  v = fmaxf(v, dpp_f<kDppRowMirror>(v));
+  return fmaxf(fmaxf(lane_f(v, 0), lane_f(v, 16)), fmaxf(lane_f(v, 32), lane_f(v, 48)));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<kDppQuadXor1>(v);
+  v += dpp_d<kDppQuadXor2>(v);
+  v += dpp_d<kDppRowHalfMirror>(v);
+  v += dpp_d<kDppRowMirror>(v);
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
+}
+
+// wave partials to LDS (one lane per wave); the caller orders them with a barrier
+template <int NT>
+__device__ __forceinline__ void wave_max2_to_lds(float a, float b, float* red, int tid) {
+  a = wave_max(a);
+  b = wave_max(b);
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = a;
+    red[NT / 64 + (tid >> 6)] = b;
+  }
+}
+template <int NT>
+__device__ __forceinline__ void lds_max2(const float* red, float& a, float& b) {
+  a = red[0];
+  b = red[NT / 64];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) {
+    a = fmaxf(a, red[i]);
+    b = fmaxf(b, red[NT / 64 + i]);
+  }
+}
+template <int NT>
+__device__ __forceinline__ double lds_sum(const double* red) {
+  double v = red[0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) v += red[i];
+  return v;
+}
+
 template <int NT>
 __device__ __forceinline__ void block_max2(float& a, float& b, float* red, int tid) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    a = fmaxf(a, __shfl_xor(a, off));
-    b = fmaxf(b, __shfl_xor(b, off));
-  }
-  constexpr int NW = NT / 64;
-  if constexpr (NW > 1) {
-    const int w = tid >> 6, l = tid & 63;
-    if (l == 0) {
-      red[w] = a;
-      red[NW + w] = b;
-    }
-    __syncthreads();
-    a = red[0];
-    b = red[NW];
-#pragma unroll
-    for (int i = 1; i < NW; ++i) {
-      a = fmaxf(a, red[i]);
-      b = fmaxf(b, red[NW + i]);
-    }
-    __syncthreads();
-  }
+  wave_max2_to_lds<NT>(a, b, red, tid);
+  __syncthreads();
+  lds_max2<NT>(red, a, b);
+  __syncthreads();
 }
 
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* red, int tid) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  constexpr int NW = NT / 64;
-  if constexpr (NW > 1) {
-    const int w = tid >> 6, l = tid & 63;
-    if (l == 0) red[w] = v;
-    __syncthreads();
-    v = red[0];
-#pragma unroll
-    for (int i = 1; i < NW; ++i) v += red[i];
-    __syncthreads();
-  }
+  v = wave_sum(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  v = lds_sum<NT>(red);
+  __syncthreads();
   return v;
 }
 
 // sum over the four consecutive lanes of a 4 x 4 region (identical in all four)
 __device__ __forceinline__ float quad_sum(float v) {
-  v += __shfl_xor(v, 1);
-  return v + __shfl_xor(v, 2);
+  v += dpp_f<kDppQuadXor1>(v);
+  return v + dpp_f<kDppQuadXor2>(v);
 }
 
 __device__ __forceinline__ cx<float> ld(const float2* p, size_t i) {
@@ -240,17 +286,20 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
     z2m = fmaxf(z2m, norm2(zz));
     A[(r0 + e / BS) * LS + c0 + e % BS] = mul(q, zz);
   }
-  block_max2<NT>(q2m, z2m, redf, tid);
-  const float qqmax = q2m, zmax = z2m;
+  // wave maxima go to LDS now; the barriers of the transforms order them
+  // before they are read in the per-pixel phase
+  wave_max2_to_lds<NT>(q2m, z2m, redf, tid);
   __syncthreads();
   fft2_forward<float, M>(A, tws, tid);
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < PX; ++e) acc += (double)project_amp<M>(A[(r0 + e / BS) * LS + c0 + e % BS], amp[e]);
-  const double tot = block_sum<NT>(acc, redd, tid);  // its barriers also order the projection
-  if (tid == 0 && a.phi) a.phi[s] = tot / (2.0 * M * M);
+  acc = wave_sum(acc);
+  if ((tid & 63) == 0) redd[tid >> 6] = acc;
   __syncthreads();
   fft2_inverse<float, M>(A, tws, tid);
+  float qqmax, zmax;
+  lds_max2<NT>(redf, qqmax, zmax);
   auto rf = [&](int e) { return A[(r0 + e / BS) * LS + c0 + e % BS]; };
   if constexpr (Px<M>::CACHE) {
     pixel_update<M, L>(a, s, r0, c0, [&](int e) { return qc[e]; }, [&](int e) { return zc[e]; }, rf,
@@ -259,6 +308,7 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
     pixel_update<M, L>(a, s, r0, c0, [&](int e) { return ld(a.probe, paddr(e)); },
                        [&](int e) { return ld(a.obj, gaddr(e)); }, rf, qqmax, zmax);
   }
+  if (tid == 0 && a.phi) a.phi[s] = lds_sum<NT>(redd) / (2.0 * M * M);
   __syncthreads();  // LDS is reused by the next slot of a persistent loop
 }
 
@@ -331,8 +381,8 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
         accn[e] = cx<float>{0.f, 0.f};
         accd[e] = 0.f;
       }
-      // four slots per round: every load of the round is issued before any add
-      constexpr int U = 4;
+      // U slots per round: every load of the round is issued before any add
+      constexpr int U = FNT >= 1024 ? 2 : 4;
       for (int i0 = 0; i0 < cnt; i0 += U) {
         cx<float> vn[U][PER];
         float vd[U][PER];
@@ -384,8 +434,8 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
     cx<float> mac{0.f, 0.f};
     float eac = 0.f;
     if (live) {
-      // eight slots per round: the round's loads are all issued before its adds
-      constexpr int U = 8;
+      // U slots per round: the round's loads are all issued before its adds
+      constexpr int U = FNT >= 1024 ? 4 : 8;
       for (int s0 = s_lo; s0 < s_hi; s0 += U) {
         cx<float> vm[U];
         float ve[U];
@@ -834,24 +884,39 @@ __global__ __launch_bounds__(256) void k_slot_info(const int* idx, const int2* p
     default: return hipErrorInvalidValue;                                       \
   }
 
+// With timing events the launch goes through hipExtLaunchKernel, which
+// timestamps the kernel's own execution (the dispatch is not included).
 template <int M, int L>
-static hipError_t patch_step_l(const StepArgs& a, hipStream_t s) {
+static hipError_t patch_step_l(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (e0) {
+    StepArgs aa = a;
+    void* args[] = {&aa};
+    return hipExtLaunchKernel((const void*)k_patch_step<M, L>, dim3(a.b), dim3(Plan<M>::NT), args,
+                              0, s, e0, e1, 0);
+  }
   hipLaunchKernelGGL((k_patch_step<M, L>), dim3(a.b), dim3(Plan<M>::NT), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_patch_step(int m, int L, const StepArgs& a, hipStream_t s) {
-  EMG_DISPATCH_ML(m, L, patch_step_l, a, s);
+hipError_t launch_patch_step(int m, int L, const StepArgs& a, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
+  EMG_DISPATCH_ML(m, L, patch_step_l, a, s, e0, e1);
 }
 
 template <int M>
-static hipError_t finalize_l(const StepArgs& a, hipStream_t s) {
+static hipError_t finalize_l(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   int ntiles;
   const int items = finalize_items<M, kFinNT>(a.n, &ntiles);
+  if (e0) {
+    StepArgs aa = a;
+    void* args[] = {&aa, &ntiles};
+    return hipExtLaunchKernel((const void*)k_finalize<M>, dim3(items), dim3(kFinNT), args, 0, s, e0,
+                              e1, 0);
+  }
   hipLaunchKernelGGL(k_finalize<M>, dim3(items), dim3(kFinNT), 0, s, a, ntiles);
   return hipGetLastError();
 }
-hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s) {
-  EMG_DISPATCH_M(m, finalize_l, a, s);
+hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  EMG_DISPATCH_M(m, finalize_l, a, s, e0, e1);
 }
 
 template <int M, int L>

@@ -36,8 +36,11 @@ struct StepArgs {
   float* qqmax;      // 1
 };
 
-hipError_t launch_patch_step(int m, int L, const StepArgs& a, hipStream_t s);
-hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s);
+// e0 / e1 (optional): events timestamped at the kernel's start and end
+hipError_t launch_patch_step(int m, int L, const StepArgs& a, hipStream_t s,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 // plain path: the six patch-stage kernels (finalize is launched separately)
 hipError_t launch_plain_step(int m, int L, const StepArgs& a, hipStream_t s);
 
