@@ -29,6 +29,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "diffraction patterns/s per epoch + time to fixed misfit, fused vs plain, 1 GPU"
+WORKLOADS = {
+    "c2": "512^2 object, 64^2 probe, 40x40 jittered raster (1600 positions), Poisson 1e6 photons, "
+          "minibatch 64, 2 multigrid levels",
+    "c3": "1024^2 object, 128^2 probe, 10000-point Fermat spiral, Poisson 1e7 photons, minibatch 256, "
+          "3 multigrid levels",
+}
 
 
 def log(*a):
@@ -109,6 +115,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-target", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
+                    help="c2 (default, the headline workload) or c3 (1024^2 object, 128^2 probe, "
+                         "10000-point Fermat spiral, minibatch 256, 3 levels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
@@ -121,8 +130,8 @@ def main():
 
     torch.cuda.set_device(0)
     K, W = args.steps, args.warmup
-    log("building workload c2 ...")
-    p = synth.make_problem("c2")
+    log(f"building workload {args.workload} ...")
+    p = synth.make_problem(args.workload)
     d = torch.from_numpy(p.intensities).cuda()
     N, n, m, B = p.n_pos, p.n, p.m, p.minibatch
 
@@ -156,9 +165,9 @@ def main():
             rec.epoch(obj, probe, W + e)
         prof = rec.profile_read()
         ms, cnt = prof["persistent"]
-        kname = "k_epoch_persistent<64,2>"
+        kname = f"k_epoch_persistent<{m},{p.levels}>"
         bytes_per_launch = A_epoch
-        unit_desc = "one epoch (25 minibatches)"
+        unit_desc = f"one epoch ({len(U)} minibatches)"
         rec.close()
     else:
         rec, obj, probe = fresh("fused")
@@ -170,9 +179,9 @@ def main():
             rec.epoch(obj, probe, W + e)
         prof = rec.profile_read()
         ms, cnt = prof["patch"]
-        kname = "k_patch_step<64,2>"
+        kname = f"k_patch_step<{m},{p.levels}>"
         bytes_per_launch = N * m * m * 12 / len(U)
-        unit_desc = "one minibatch of 64 patches"
+        unit_desc = f"one minibatch of {B} patches"
         rec.close()
     avg_s = ms / 1e3 / max(cnt, 1)
     achieved = bytes_per_launch / avg_s / 1e9
@@ -186,7 +195,7 @@ def main():
     tgt_file = os.path.join(ROOT, "tests", "golden", "misfit_targets.json")
     if not args.no_target and os.path.exists(tgt_file):
         with open(tgt_file) as f:
-            tg = json.load(f).get("c2")
+            tg = json.load(f).get(args.workload)
         if tg:
             ttt = {"target": tg["target"], "oracle_epochs": tg["epochs"]}
             for path in [best, "plain"]:
@@ -209,8 +218,7 @@ def main():
         "ms_per_step": t_best,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "512^2 object, 64^2 probe, 40x40 jittered raster (1600 positions), "
-                               "Poisson 1e6 photons, minibatch 64, 2 multigrid levels",
+        "config": {"workload": WORKLOADS[args.workload],
                    "n": n, "m": m, "positions": N, "minibatch": B, "levels": p.levels,
                    "path": best, "parallelism": "single GPU"},
         "paths": paths,

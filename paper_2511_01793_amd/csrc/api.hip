@@ -57,7 +57,7 @@ struct Region {
 };
 
 struct Layout {
-  Region dperm, pos, slots, tw32, tw64, numer, pnum, pden, phi, stack, zmax, ubuf, Dbuf, scal,
+  Region dperm, pos, slots, tw32, tw64, numer, pnum, pden, pden_slot, phi, stack, zmax, ubuf, Dbuf, scal,
       bar, phi_all, gz, gq;
   int grad_chunk;
   size_t total;
@@ -82,6 +82,7 @@ Layout make_layout(const emagpie_config& c) {
   L.numer = take(B * m2 * 8);
   L.pnum = take(B * m2 * 8);
   L.pden = take(B * m2 * 4);
+  L.pden_slot = take(B * 4);
   L.phi = take(B * 8);
   L.stack = take(B * m2 * 8);
   L.zmax = take(B * 4);
@@ -128,7 +129,7 @@ struct emagpie_ctx_s {
   float2* tw32;
   double2* tw64;
   float2 *numer, *pnum, *stack;
-  float *pden, *zmax, *ubuf, *Dbuf;
+  float *pden, *pden_slot, *zmax, *ubuf, *Dbuf;
   double *phi, *phi_all;
   double* scal_d;  // [0] dp sum, [1] scratch
   int* scal_i;     // [0] bad-data flag, [1] zero-probe flag
@@ -172,6 +173,8 @@ emg::StepArgs base_args(emagpie_ctx c, void* obj, void* probe) {
   a.numer = c->numer;
   a.pnum = c->pnum;
   a.pden = c->pden;
+  // alpha_z = 1 (the ePIE probe step): |z_k|^2 + u_z = max |z_k|^2, one value per patch
+  a.pden_slot = c->cfg.alpha_z == 1.0f ? c->pden_slot : nullptr;
   a.phi = c->phi;
   a.Dbuf = c->Dbuf;
   a.stack = c->stack;
@@ -301,6 +304,7 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   ctx->numer = reinterpret_cast<float2*>(w + lay.numer.off);
   ctx->pnum = reinterpret_cast<float2*>(w + lay.pnum.off);
   ctx->pden = reinterpret_cast<float*>(w + lay.pden.off);
+  ctx->pden_slot = reinterpret_cast<float*>(w + lay.pden_slot.off);
   ctx->phi = reinterpret_cast<double*>(w + lay.phi.off);
   ctx->stack = reinterpret_cast<float2*>(w + lay.stack.off);
   ctx->zmax = reinterpret_cast<float*>(w + lay.zmax.off);

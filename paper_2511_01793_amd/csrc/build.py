@@ -18,9 +18,12 @@ SOURCES = ["kernels.hip", "api.hip"]
 
 # Packed FP32 VALU forms are disabled on purpose: every FP32 operation is a
 # scalar-lane IEEE operation.  hipcc's host pass does not know this feature
-# and says so; that message is harmless.
+# and says so; that message is harmless.  Floating-point contraction is off so
+# that every operation is rounded on its own: the same source arithmetic then
+# gives the same bits in every kernel that inlines it (all launch strategies
+# agree bitwise).
 HIPFLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]

@@ -55,27 +55,12 @@ __device__ __forceinline__ cx<T> rot90(cx<T> a) {
   return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
 }
 
-// Factorisation and thread count per probe side.  In the per-pixel phases each
-// thread owns one BS x BS pixel block, so NT = m^2 / BS^2.
+// Factorisation and workgroup size per probe side (m^2 / 4 threads, at most
+// 1024: each thread owns 2 x 2 pixel blocks in the per-pixel phases).
 template <int M> struct Plan;
-template <> struct Plan<32> { static constexpr int R1 = 8, R2 = 4, NT = 256, BS = 2; };
-template <> struct Plan<64> { static constexpr int R1 = 8, R2 = 8, NT = 1024, BS = 2; };
-template <> struct Plan<128> { static constexpr int R1 = 16, R2 = 8, NT = 1024, BS = 4; };
-
-// Top-left pixel of the block a thread owns.  With 2 x 2 blocks, four
-// consecutive lanes own the four blocks of one 4 x 4 region, so a region-wide
-// sum is two lane exchanges.
-template <int M>
-__device__ __forceinline__ void block_origin(int tid, int& r0, int& c0) {
-  if constexpr (Plan<M>::BS == 2) {
-    const int q = tid >> 2, sub = tid & 3;
-    r0 = 4 * (q / (M / 4)) + 2 * (sub >> 1);
-    c0 = 4 * (q % (M / 4)) + 2 * (sub & 1);
-  } else {
-    r0 = 4 * (tid / (M / 4));
-    c0 = 4 * (tid % (M / 4));
-  }
-}
+template <> struct Plan<32> { static constexpr int R1 = 8, R2 = 4, NT = 256; };
+template <> struct Plan<64> { static constexpr int R1 = 8, R2 = 8, NT = 1024; };
+template <> struct Plan<128> { static constexpr int R1 = 16, R2 = 8, NT = 1024; };
 
 template <int M>
 __host__ __device__ constexpr int lds_stride() { return M + 1; }

@@ -130,91 +130,84 @@ __device__ __forceinline__ void st(float2* p, size_t i, cx<float> v) { p[i] = ma
 
 template <int M>
 struct Px {
-  static constexpr int BS = Plan<M>::BS, PX = BS * BS, NT = Plan<M>::NT, LS = lds_stride<M>();
-  static constexpr int NSB = PX / 4;  // 2 x 2 sub-blocks per thread block
-  // small blocks keep the thread's probe / object values in registers from the
-  // gather to the numerators; 4 x 4 blocks reload them (register budget)
-  static constexpr bool CACHE = BS == 2;
+  static constexpr int NT = Plan<M>::NT, LS = lds_stride<M>();
+  // every thread owns 2 x 2 pixel blocks: one per round, ROUNDS rounds
+  // (quadrants of 64 x 64 when the tile has more pixels than 4 x NT)
+  static constexpr int ROUNDS = M * M / (4 * NT);
+  static constexpr int PX = 4 * ROUNDS;  // pixels per thread
+  static constexpr int QW = (ROUNDS == 1 ? M : 64) / 4;  // 4 x 4 regions per row of a round
+  // one round: keep the thread's probe / object values in registers from the
+  // gather to the numerators; several rounds reload them (register budget)
+  static constexpr bool CACHE = ROUNDS == 1;
 };
 
+// Pixel e of a thread: round e / 4, position (e / 2 % 2, e % 2) inside that
+// round's 2 x 2 block.  Four consecutive lanes own the four 2 x 2 blocks of one
+// 4 x 4 region, so a region-wide sum is two quad lane exchanges.
+template <int M>
+__device__ __forceinline__ void pix_rc(int tid, int e, int& r, int& c) {
+  constexpr int QW = Px<M>::QW;
+  const int q = tid >> 2, sub = tid & 3, round = e >> 2;
+  r = 4 * (q / QW) + 2 * (sub >> 1) + ((e >> 1) & 1);
+  c = 4 * (q % QW) + 2 * (sub & 1) + (e & 1);
+  if constexpr (Px<M>::ROUNDS > 1) {
+    r += 64 * (round >> 1);
+    c += 64 * (round & 1);
+  }
+}
+
 // ---------------------------------------------------------------------------
-// per-pixel surrogate algebra for one patch (thread owns a BS x BS block)
-//   qf(e), zf(e), rf(e): probe, object window and revised exit wave at pixel
-//   e = i * BS + j of the block whose top-left pixel is (r0, c0)
+// per-pixel surrogate algebra for one patch
+//   qf(e), zf(e), rf(e): probe, object window and revised exit wave at the
+//   thread's pixel e (see pix_rc); one round (2 x 2 block) at a time
 // ---------------------------------------------------------------------------
 template <int M, int L, class QF, class ZF, class RF>
-__device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int r0, int c0, QF qf, ZF zf,
-                                             RF rf, float qqmax, float zmax) {
-  constexpr int BS = Px<M>::BS, NSB = Px<M>::NSB;
-  // pass 1: 2 x 2 sub-block sums of g = conj(Q)(R - Q z), D, u, Q, |Q|^2
-  cx<float> Gs[NSB], Qs[NSB];
-  float Ds[NSB], Us[NSB], Q2s[NSB];
+__device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, QF qf, ZF zf, RF rf,
+                                             float qqmax, float zmax) {
+  const size_t base = (size_t)s * M * M;
+  const bool slot_den = a.pden_slot != nullptr;
 #pragma unroll
-  for (int b = 0; b < NSB; ++b) {
-    Gs[b] = Qs[b] = cx<float>{0.f, 0.f};
-    Ds[b] = Us[b] = Q2s[b] = 0.f;
-  }
-  if constexpr (L >= 2) {
+  for (int rd = 0; rd < Px<M>::ROUNDS; ++rd) {
+    // pass 1: block sums of g = conj(Q)(R - Q z), D, u, Q, |Q|^2
+    cx<float> Gs{0.f, 0.f}, Qs{0.f, 0.f};
+    float Ds = 0.f, Us = 0.f, Q2s = 0.f;
+    if constexpr (L >= 2) {
 #pragma unroll
-    for (int i = 0; i < BS; ++i) {
-#pragma unroll
-      for (int j = 0; j < BS; ++j) {
-        const int e = i * BS + j, sb = (i >> 1) * (BS / 2) + (j >> 1);
+      for (int e4 = 0; e4 < 4; ++e4) {
+        const int e = 4 * rd + e4;
         const cx<float> q = qf(e), zz = zf(e), R = rf(e);
         const float q2 = norm2(q);
         const float u = a.alpha * (qqmax - q2);
-        const cx<float> g = cmulc(q, sub(R, mul(q, zz)));
-        Gs[sb] = add(Gs[sb], g);
-        Ds[sb] += q2 + u;
-        Us[sb] += u;
-        Qs[sb] = add(Qs[sb], q);
-        Q2s[sb] += q2;
+        Gs = add(Gs, cmulc(q, sub(R, mul(q, zz))));
+        Ds += q2 + u;
+        Us += u;
+        Qs = add(Qs, q);
+        Q2s += q2;
       }
     }
-  }
-  // coarse corrections per 2 x 2 sub-block: block-ratio form of the restricted
-  // coarse solve; three levels recurse once more over each 4 x 4 region
-  cx<float> cc[NSB];
-#pragma unroll
-  for (int b = 0; b < NSB; ++b) cc[b] = cx<float>{0.f, 0.f};
-  if constexpr (L == 2) {
-#pragma unroll
-    for (int b = 0; b < NSB; ++b)
-      if (Ds[b] > 0.f) cc[b] = scale(Gs[b], 1.f / Ds[b]);
-  } else if constexpr (L == 3) {
-    float wts[NSB];
-#pragma unroll
-    for (int b = 0; b < NSB; ++b) wts[b] = Q2s[b] > 0.f ? norm2(Qs[b]) / (4.f * Q2s[b]) : 0.f;
-    cx<float> G2{0.f, 0.f};
-    float D2 = 0.f;
-    if constexpr (NSB == 4) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        G2 = add(G2, scale(Gs[b], wts[b]));
-        D2 += wts[b] * Ds[b];
-      }
-    } else {
-      G2 = cx<float>{quad_sum(wts[0] * Gs[0].re), quad_sum(wts[0] * Gs[0].im)};
-      D2 = quad_sum(wts[0] * Ds[0]);
+    // coarse correction of this 2 x 2 block: block-ratio form of the restricted
+    // coarse solve; three levels recurse once more over the 4 x 4 region
+    cx<float> cc{0.f, 0.f};
+    if constexpr (L == 2) {
+      if (Ds > 0.f) cc = scale(Gs, 1.f / Ds);
+    } else if constexpr (L == 3) {
+      const float w = Q2s > 0.f ? norm2(Qs) / (4.f * Q2s) : 0.f;
+      const cx<float> G2{quad_sum(w * Gs.re), quad_sum(w * Gs.im)};
+      const float D2 = quad_sum(w * Ds);
+      const cx<float> c2 = D2 > 0.f ? scale(G2, 1.f / D2) : cx<float>{0.f, 0.f};
+      if (Ds > 0.f) cc = scale(add(Gs, scale(c2, Us)), 1.f / Ds);
     }
-    const cx<float> c2 = D2 > 0.f ? scale(G2, 1.f / D2) : cx<float>{0.f, 0.f};
+    // pass 2: numerators and denominators
 #pragma unroll
-    for (int b = 0; b < NSB; ++b)
-      if (Ds[b] > 0.f) cc[b] = scale(add(Gs[b], scale(c2, Us[b])), 1.f / Ds[b]);
-  }
-  // pass 2: numerators and denominators
-  const size_t base = (size_t)s * M * M;
-#pragma unroll
-  for (int i = 0; i < BS; ++i) {
-#pragma unroll
-    for (int j = 0; j < BS; ++j) {
-      const int e = i * BS + j, sb = (i >> 1) * (BS / 2) + (j >> 1);
-      const int r = r0 + i, c = c0 + j;
+    for (int e4 = 0; e4 < 4; ++e4) {
+      const int e = 4 * rd + e4;
+      int r, c;
+      pix_rc<M>(tid, e, r, c);
       const cx<float> q = qf(e), zz = zf(e), R = rf(e);
       const float q2 = norm2(q);
       const float u = a.alpha * (qqmax - q2);
       const float D = q2 + u;
-      const cx<float> zp = add(zz, cc[sb]);
+      const cx<float> zp = add(zz, cc);
       const cx<float> N = add(cmulc(q, R), scale(zp, u));
       const size_t o = base + (size_t)r * M + c;
       if (a.zplus) {
@@ -224,22 +217,17 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int r0, i
         const float uz = a.alpha_z * (zmax - z2);
         st(a.numer, o, N);
         st(a.pnum, o, add(cmulc(zz, R), scale(q, uz)));
-        a.pden[o] = z2 + uz;
+        if (!slot_den) a.pden[o] = z2 + uz;
         if (s == 0) a.Dbuf[r * M + c] = D;
       }
     }
   }
+  // alpha_z = 1: the probe denominator |z_k|^2 + u_z = max |z_k|^2 is one number per patch
+  if (slot_den && !a.zplus && tid == 0) a.pden_slot[s] = zmax;
 }
 
 // modulus projection of one pixel in transform order: Psi' = a Psi/|Psi|
 // (a where Psi = 0), scaled by 1/m^2; returns (|Psi| - a)^2
-template <int M>
-__device__ __forceinline__ float project_amp(cx<float>& P, float amp);
-template <int M>
-__device__ __forceinline__ float project_px(cx<float>& P, float dval) {
-  return project_amp<M>(P, sqrtf(fmaxf(dval, 0.f)));
-}
-
 template <int M>
 __device__ __forceinline__ float project_amp(cx<float>& P, float amp) {
   const float mag = sqrtf(norm2(P));
@@ -247,6 +235,10 @@ __device__ __forceinline__ float project_amp(cx<float>& P, float amp) {
   const cx<float> o = mag > 0.f ? scale(P, amp / mag) : cx<float>{amp, 0.f};
   P = scale(o, 1.f / float(M * M));
   return diff * diff;
+}
+template <int M>
+__device__ __forceinline__ float project_px(cx<float>& P, float dval) {
+  return project_amp<M>(P, sqrtf(fmaxf(dval, 0.f)));
 }
 
 // ---------------------------------------------------------------------------
@@ -256,35 +248,49 @@ template <int M, int L>
 __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* A,
                                            const cx<float>* tws, float* redf, double* redd,
                                            int tid) {
-  constexpr int BS = Px<M>::BS, PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
+  constexpr int PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
   const int4 sl = a.slot[s];
   const int k = sl.x;
-  const int2 pk = make_int2(sl.y, sl.z);
   const size_t n = (size_t)a.n;
+  const float2* zwin = a.obj + (size_t)sl.y * n + sl.z;
   const float* dk = a.dperm + (size_t)k * M * M;
-  int r0, c0;
-  block_origin<M>(tid, r0, c0);
-  auto gaddr = [&](int e) { return (size_t)(pk.x + r0 + e / BS) * n + pk.y + c0 + e % BS; };
-  auto paddr = [&](int e) { return (size_t)(r0 + e / BS) * M + c0 + e % BS; };
+  auto lds = [&](int e) -> cx<float>& {
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
+    return A[r * LS + c];
+  };
+  auto qld = [&](int e) {
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
+    return ld(a.probe, (size_t)r * M + c);
+  };
+  auto zld = [&](int e) {
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
+    return ld(zwin, (size_t)r * n + c);
+  };
   // all global loads of the patch are issued here, before any dependent work
   cx<float> qc[Px<M>::CACHE ? PX : 1], zc[Px<M>::CACHE ? PX : 1];
   float amp[PX];
   float q2m = 0.f, z2m = 0.f;
 #pragma unroll
-  for (int e = 0; e < PX; ++e) amp[e] = dk[paddr(e)];
+  for (int e = 0; e < PX; ++e) {
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
+    amp[e] = dk[r * M + c];
+  }
 #pragma unroll
-  for (int e = 0; e < PX; ++e) amp[e] = sqrtf(fmaxf(amp[e], 0.f));  // consumed before the barrier
+  for (int e = 0; e < PX; ++e) amp[e] = sqrtf(fmaxf(amp[e], 0.f));
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
-    const cx<float> q = ld(a.probe, paddr(e));
-    const cx<float> zz = ld(a.obj, gaddr(e));
+    const cx<float> q = qld(e), zz = zld(e);
     if constexpr (Px<M>::CACHE) {
       qc[e] = q;
       zc[e] = zz;
     }
     q2m = fmaxf(q2m, norm2(q));
     z2m = fmaxf(z2m, norm2(zz));
-    A[(r0 + e / BS) * LS + c0 + e % BS] = mul(q, zz);
+    lds(e) = mul(q, zz);
   }
   // wave maxima go to LDS now; the barriers of the transforms order them
   // before they are read in the per-pixel phase
@@ -293,20 +299,19 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
   fft2_forward<float, M>(A, tws, tid);
   double acc = 0.0;
 #pragma unroll
-  for (int e = 0; e < PX; ++e) acc += (double)project_amp<M>(A[(r0 + e / BS) * LS + c0 + e % BS], amp[e]);
+  for (int e = 0; e < PX; ++e) acc += (double)project_amp<M>(lds(e), amp[e]);
   acc = wave_sum(acc);
   if ((tid & 63) == 0) redd[tid >> 6] = acc;
   __syncthreads();
   fft2_inverse<float, M>(A, tws, tid);
   float qqmax, zmax;
   lds_max2<NT>(redf, qqmax, zmax);
-  auto rf = [&](int e) { return A[(r0 + e / BS) * LS + c0 + e % BS]; };
+  auto rf = [&](int e) { return lds(e); };
   if constexpr (Px<M>::CACHE) {
-    pixel_update<M, L>(a, s, r0, c0, [&](int e) { return qc[e]; }, [&](int e) { return zc[e]; }, rf,
+    pixel_update<M, L>(a, s, tid, [&](int e) { return qc[e]; }, [&](int e) { return zc[e]; }, rf,
                        qqmax, zmax);
   } else {
-    pixel_update<M, L>(a, s, r0, c0, [&](int e) { return ld(a.probe, paddr(e)); },
-                       [&](int e) { return ld(a.obj, gaddr(e)); }, rf, qqmax, zmax);
+    pixel_update<M, L>(a, s, tid, qld, zld, rf, qqmax, zmax);
   }
   if (tid == 0 && a.phi) a.phi[s] = lds_sum<NT>(redd) / (2.0 * M * M);
   __syncthreads();  // LDS is reused by the next slot of a persistent loop
@@ -442,9 +447,10 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const bool in = s0 + u < s_hi;
-          const size_t o = (size_t)(in ? s0 + u : s_lo) * M * M + r;
+          const int sl = in ? s0 + u : s_lo;
+          const size_t o = (size_t)sl * M * M + r;
           vm[u] = in ? ld(a.pnum, o) : cx<float>{0.f, 0.f};
-          ve[u] = in ? a.pden[o] : 0.f;
+          ve[u] = in ? (a.pden_slot ? a.pden_slot[sl] : a.pden[o]) : 0.f;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -585,17 +591,16 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_probe_prep(StepArgs a) {
 template <int M>
 __global__ __launch_bounds__(Plan<M>::NT) void k_gather(StepArgs a) {
   __shared__ float redf[32];
-  constexpr int BS = Px<M>::BS, PX = Px<M>::PX;
+  constexpr int PX = Px<M>::PX;
   const int tid = threadIdx.x, s = blockIdx.x;
-  const int2 pk = make_int2(a.slot[s].y, a.slot[s].z);
-  int r0, c0;
-  block_origin<M>(tid, r0, c0);
+  const float2* zwin = a.obj + (size_t)a.slot[s].y * a.n + a.slot[s].z;
   float z2m = 0.f, dummy = 0.f;
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
-    const int r = r0 + e / BS, c = c0 + e % BS;
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
     const cx<float> q = ld(a.probe, (size_t)r * M + c);
-    const cx<float> zz = ld(a.obj, (size_t)(pk.x + r) * a.n + pk.y + c);
+    const cx<float> zz = ld(zwin, (size_t)r * a.n + c);
     z2m = fmaxf(z2m, norm2(zz));
     st(a.stack, (size_t)s * M * M + r * M + c, mul(q, zz));
   }
@@ -621,16 +626,16 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_fft(StepArgs a) {
 template <int M>
 __global__ __launch_bounds__(Plan<M>::NT) void k_project(StepArgs a) {
   __shared__ double redd[16];
-  constexpr int BS = Px<M>::BS, PX = Px<M>::PX, NT = Px<M>::NT;
+  constexpr int PX = Px<M>::PX, NT = Px<M>::NT;
   const int tid = threadIdx.x, s = blockIdx.x;
   float2* X = a.stack + (size_t)s * M * M;
   const float* dk = a.dperm + (size_t)a.slot[s].x * M * M;
-  int r0, c0;
-  block_origin<M>(tid, r0, c0);
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
-    const size_t o = (size_t)(r0 + e / BS) * M + c0 + e % BS;
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
+    const size_t o = (size_t)r * M + c;
     cx<float> P = ld(X, o);
     acc += (double)project_px<M>(P, dk[o]);
     st(X, o, P);
@@ -641,18 +646,23 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_project(StepArgs a) {
 
 template <int M, int L>
 __global__ __launch_bounds__(Plan<M>::NT) void k_numerators(StepArgs a) {
-  constexpr int BS = Px<M>::BS;
   const int tid = threadIdx.x, s = blockIdx.x;
-  const int2 pk = make_int2(a.slot[s].y, a.slot[s].z);
   const size_t n = (size_t)a.n;
+  const float2* zwin = a.obj + (size_t)a.slot[s].y * n + a.slot[s].z;
   const float2* Rg = a.stack + (size_t)s * M * M;
-  int r0, c0;
-  block_origin<M>(tid, r0, c0);
-  auto paddr = [&](int e) { return (size_t)(r0 + e / BS) * M + c0 + e % BS; };
-  auto gaddr = [&](int e) { return (size_t)(pk.x + r0 + e / BS) * n + pk.y + c0 + e % BS; };
-  pixel_update<M, L>(a, s, r0, c0, [&](int e) { return ld(a.probe, paddr(e)); },
-                     [&](int e) { return ld(a.obj, gaddr(e)); },
-                     [&](int e) { return ld(Rg, paddr(e)); }, a.qqmax[0], a.zmax[s]);
+  auto pa = [&](int e) {
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
+    return (size_t)r * M + c;
+  };
+  auto ga = [&](int e) {
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
+    return (size_t)r * n + c;
+  };
+  pixel_update<M, L>(a, s, tid, [&](int e) { return ld(a.probe, pa(e)); },
+                     [&](int e) { return ld(zwin, ga(e)); }, [&](int e) { return ld(Rg, pa(e)); },
+                     a.qqmax[0], a.zmax[s]);
 }
 
 // ---------------------------------------------------------------------------
@@ -666,17 +676,16 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_misfit(const float2* obj, int n
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ double redd[16];
-  constexpr int BS = Px<M>::BS, PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
+  constexpr int PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
   const int tid = threadIdx.x, k = blockIdx.x;
   const int2 pk = pos[k];
   const float* dk = dperm + (size_t)k * M * M;
-  int r0, c0;
-  block_origin<M>(tid, r0, c0);
   stage_twiddles<M>(tw, tws, tid);
   float dv[PX];
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
-    const int r = r0 + e / BS, c = c0 + e % BS;
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
     dv[e] = dk[r * M + c];
     A[r * LS + c] = mul(ld(probe, (size_t)r * M + c), ld(obj, (size_t)(pk.x + r) * n + pk.y + c));
   }
@@ -684,7 +693,11 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_misfit(const float2* obj, int n
   fft2_forward<float, M>(A, tws, tid);
   double acc = 0.0;
 #pragma unroll
-  for (int e = 0; e < PX; ++e) acc += (double)project_px<M>(A[(r0 + e / BS) * LS + c0 + e % BS], dv[e]);
+  for (int e = 0; e < PX; ++e) {
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
+    acc += (double)project_px<M>(A[r * LS + c], dv[e]);
+  }
   const double tot = block_sum<NT>(acc, redd, tid);
   if (tid == 0) phi_all[k] = tot / (2.0 * M * M);
 }
@@ -703,16 +716,15 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_patch(GradArgs g, int k0) 
   __shared__ cx<T> A[M * lds_stride<M>()];
   __shared__ cx<T> tws[M];
   __shared__ double redd[16];
-  constexpr int BS = Px<M>::BS, PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
+  constexpr int PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
   const int tid = threadIdx.x, s = blockIdx.x, k = k0 + s;
   const int2 pk = g.pos[k];
   const size_t n = (size_t)g.n;
-  int r0, c0;
-  block_origin<M>(tid, r0, c0);
   for (int j = tid; j < M; j += NT) tws[j] = ldT<T>(g.tw, j);
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
-    const int r = r0 + e / BS, c = c0 + e % BS;
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
     A[r * LS + c] = mul(ldT<T>(g.probe, (size_t)r * M + c), ldT<T>(g.obj, (pk.x + r) * n + pk.y + c));
   }
   __syncthreads();
@@ -723,7 +735,8 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_patch(GradArgs g, int k0) 
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
-    const int r = r0 + e / BS, c = c0 + e % BS;
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
     const cx<T> P = A[r * LS + c];
     const T amp = sqrt(fmax(T(dk[r * M + c]), T(0)));
     const T mag = sqrt(norm2(P));
@@ -737,7 +750,8 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_patch(GradArgs g, int k0) 
   const size_t base = (size_t)s * M * M;
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
-    const int r = r0 + e / BS, c = c0 + e % BS;
+    int r, c;
+    pix_rc<M>(tid, e, r, c);
     const cx<T> ev = A[r * LS + c];
     const cx<T> q = ldT<T>(g.probe, (size_t)r * M + c);
     const cx<T> zz = ldT<T>(g.obj, (pk.x + r) * n + pk.y + c);

@@ -25,6 +25,7 @@ struct StepArgs {
   float2* numer;     // b x m^2 object numerators conj(Q) R + u z'
   float2* pnum;      // b x m^2 probe numerators conj(z) R + u_z Q
   float* pden;       // b x m^2 probe denominators |z|^2 + u_z
+  float* pden_slot;  // b: when not null (alpha_z = 1) the denominator is max |z_k|^2 per slot
   double* phi;       // b sampled misfit terms
   float* Dbuf;       // m^2 object denominators |Q|^2 + u (written by slot 0)
   double* sampled;   // nullable accumulator of sum phi
