@@ -108,6 +108,72 @@ def cpu_baseline(p, budget_s=10.0):
                       f"FP64 NumPy, single thread, {dt:.1f} s"}
 
 
+def bench_group(K, W):
+    """16 uneven independent reconstructions: one group epoch (all instances, batched
+    launches, one captured graph) against the same instances swept one after another."""
+    import torch
+    import paper_2511_01793_amd.emagpie as E
+    from paper_2511_01793_amd import synth
+    log("building workload c5 (16 instances) ...")
+    ps = synth.make_c5()
+    total = sum(p.n_pos for p in ps)
+
+    def members(path):
+        recs, objs, probes = [], [], []
+        for i, p in enumerate(ps):
+            d = torch.from_numpy(p.intensities).cuda()
+            rec = E.Reconstruction(p.positions, d, p.n, minibatch=p.minibatch, levels=p.levels,
+                                   alpha=p.alpha, alpha_z=p.alpha_z, path=path, seed=p.seed)
+            obj = torch.from_numpy(p.object_init).cuda()
+            probe = torch.from_numpy(p.probe_init).cuda()
+            rec.normalize_probe(probe)
+            recs.append(rec)
+            objs.append(obj)
+            probes.append(probe)
+            del d
+        return recs, objs, probes
+
+    recs, objs, probes = members("graph")
+    for e in range(W):
+        for r, o, q in zip(recs, objs, probes):
+            r.epoch(o, q, e)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(K):
+        for r, o, q in zip(recs, objs, probes):
+            r.epoch(o, q, W + e)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / K
+    log(f"one by one (graph each): {t_seq * 1e3:.3f} ms per sweep of all 16, {total / t_seq:.0f} patterns/s")
+    grp = E.Group(recs)
+    for e in range(W):
+        grp.epoch(objs, probes, e)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(K):
+        grp.epoch(objs, probes, W + e)
+    torch.cuda.synchronize()
+    t_grp = (time.perf_counter() - t0) / K
+    log(f"group: {t_grp * 1e3:.3f} ms per sweep of all 16, {total / t_grp:.0f} patterns/s")
+    A = 0
+    for p in ps:
+        A += algorithmic_bytes_epoch(p.positions, E.permutation(p.seed, 0, p.n_pos), p.n, p.m,
+                                     p.minibatch)[0]
+    grp.close()
+    for r in recs:
+        r.close()
+    return {"metric": METRIC, "value": total / t_grp, "unit": "patterns/s", "n_gpus": 1,
+            "steps": K, "warmup": W, "ms_per_step": t_grp * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "16 uneven independent reconstructions (objects 256-1024^2, "
+                                   "probes 64^2/128^2, 400-4096 positions, Poisson 1e5-1e7, "
+                                   "minibatch 64, 2 levels)",
+                       "instances": [[p.n, p.m, p.n_pos] for p in ps], "positions": total},
+            "one_by_one_ms": t_seq * 1e3, "group_speedup": t_seq / t_grp,
+            "epoch_algorithmic_bytes": A,
+            "epoch_hbm_roofline_frac": A / t_grp / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,7 +181,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-target", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
                     help="c2 (default, the headline workload) or c3 (1024^2 object, 128^2 probe, "
                          "10000-point Fermat spiral, minibatch 256, 3 levels)")
     args = ap.parse_args()
@@ -130,6 +196,9 @@ def main():
 
     torch.cuda.set_device(0)
     K, W = args.steps, args.warmup
+    if args.workload == "c5":
+        print(json.dumps(bench_group(K, W)))
+        return
     log(f"building workload {args.workload} ...")
     p = synth.make_problem(args.workload)
     d = torch.from_numpy(p.intensities).cuda()

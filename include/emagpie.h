@@ -182,6 +182,31 @@ emagpie_status emagpie_profile_enable(emagpie_ctx ctx, int32_t enable);
  */
 emagpie_status emagpie_profile_read(emagpie_ctx ctx, double* ms3_host, int64_t* count3_host);
 
+/*
+ * Many independent reconstructions advanced together (batched instances).
+ * A group binds n_inst existing contexts (each made by emagpie_init with its
+ * own configuration, data and workspace; sizes and probe sides may differ).
+ * emagpie_group_epoch runs one sweep of every instance: step j processes
+ * minibatch j of every instance that has one, with one patch-stage launch
+ * and one finalize launch per probe-size class covering all instances, the
+ * whole sweep replayed from a captured hipGraph whose probe-size classes run
+ * as parallel branches.  Each instance's arithmetic is exactly that of
+ * emagpie_epoch on its own context (same scan order for the same epoch), so
+ * the results are bitwise identical to running the instances one by one.
+ * The group workspace (device, 256-byte aligned, emagpie_group_workspace_size
+ * bytes) holds the per-step argument records, work lists and scan orders; it
+ * is caller-owned and must outlive the group, as must the contexts.
+ */
+typedef struct emagpie_group_s* emagpie_group;
+emagpie_status emagpie_group_workspace_size(int32_t n_inst, const emagpie_ctx* ctxs, size_t* bytes);
+emagpie_status emagpie_group_create(emagpie_group* out, int32_t n_inst, const emagpie_ctx* ctxs,
+                                    void* workspace_dev, size_t workspace_bytes, void* stream);
+/* obj_devs / probe_devs: n_inst device pointers (host array); sampled_misfit_dev:
+   nullable, n_inst doubles overwritten with each instance's sampled misfit */
+emagpie_status emagpie_group_epoch(emagpie_group g, void* const* obj_devs, void* const* probe_devs,
+                                   int64_t epoch, double* sampled_misfit_dev, void* stream);
+emagpie_status emagpie_group_destroy(emagpie_group g);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* emagpie_last_error(void);
 

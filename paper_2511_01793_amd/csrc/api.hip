@@ -595,3 +595,275 @@ emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* pr
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// groups of independent reconstructions
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GroupClass {
+  int m, L;
+  std::vector<int> inst;
+  std::vector<size_t> patch_off, fin_off;  // per step: offset into the work arrays
+  std::vector<int> patch_n, fin_n;         // per step: blocks
+};
+
+struct GroupLayout {
+  size_t args, slots, work, total;
+  int steps;
+  std::vector<size_t> slot_off;
+  std::vector<GroupClass> classes;
+  std::vector<int2> work_host;  // all work lists, concatenated
+};
+
+emagpie_status plan_group(int32_t n_inst, const emagpie_ctx* ctxs, GroupLayout* G) {
+  if (n_inst < 1 || !ctxs) return fail(EMAGPIE_E_ARG, "a group needs at least one context");
+  G->steps = 0;
+  G->slot_off.assign(n_inst, 0);
+  size_t nslots = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    if (!ctxs[i]) return fail(EMAGPIE_E_ARG, "null context in group");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(EMAGPIE_E_ARG, "a context appears twice in the group");
+    const emagpie_config& c = ctxs[i]->cfg;
+    G->slot_off[i] = nslots;
+    nslots += (size_t)c.n_pos;
+    G->steps = std::max(G->steps, (c.n_pos + c.minibatch - 1) / c.minibatch);
+  }
+  G->classes.clear();
+  for (int i = 0; i < n_inst; ++i) {
+    const emagpie_config& c = ctxs[i]->cfg;
+    GroupClass* cls = nullptr;
+    for (auto& k : G->classes)
+      if (k.m == c.m && k.L == c.levels) cls = &k;
+    if (!cls) {
+      G->classes.push_back(GroupClass{c.m, c.levels, {}, {}, {}, {}, {}});
+      cls = &G->classes.back();
+    }
+    cls->inst.push_back(i);
+  }
+  G->work_host.clear();
+  for (auto& k : G->classes) {
+    for (int j = 0; j < G->steps; ++j) {
+      k.patch_off.push_back(G->work_host.size());
+      for (int i : k.inst) {
+        const emagpie_config& c = ctxs[i]->cfg;
+        const int b = std::min(c.minibatch, c.n_pos - j * c.minibatch);
+        for (int s = 0; s < b; ++s) G->work_host.push_back(make_int2(j * n_inst + i, s));
+      }
+      k.patch_n.push_back((int)(G->work_host.size() - k.patch_off.back()));
+      k.fin_off.push_back(G->work_host.size());
+      for (int i : k.inst) {
+        const emagpie_config& c = ctxs[i]->cfg;
+        if (j * c.minibatch >= c.n_pos) continue;
+        int items = 0;
+        if (emg::finalize_item_count(c.m, c.n, &items) != hipSuccess)
+          return fail(EMAGPIE_E_SHAPE, "unsupported probe size in group");
+        for (int t = 0; t < items; ++t) G->work_host.push_back(make_int2(j * n_inst + i, t));
+      }
+      k.fin_n.push_back((int)(G->work_host.size() - k.fin_off.back()));
+    }
+  }
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = cur;
+    cur += align256(bytes);
+    return o;
+  };
+  G->args = take((size_t)G->steps * n_inst * sizeof(emg::StepArgs));
+  G->slots = take(nslots * sizeof(int4));
+  G->work = take(G->work_host.size() * sizeof(int2));
+  G->total = cur;
+  return EMAGPIE_OK;
+}
+
+}  // namespace
+
+struct emagpie_group_s {
+  int n;
+  std::vector<emagpie_ctx> ctx;
+  GroupLayout lay;
+  uint8_t* ws = nullptr;
+  emg::StepArgs* args_dev = nullptr;
+  int4* slots_dev = nullptr;
+  int2* work_dev = nullptr;
+  std::vector<emg::StepArgs> args_host;
+  std::vector<void*> a_obj, a_probe;  // pointers the argument table was built for
+  double* a_sampled = nullptr;
+  bool args_valid = false;
+  std::vector<int32_t> perm_host;
+  int4* pinned[2] = {nullptr, nullptr};
+  hipEvent_t pin_ev[2] = {nullptr, nullptr};
+  int pin_slot = 0;
+  std::vector<hipStream_t> streams;  // [0] capture origin, [1..] one per class
+  std::vector<hipEvent_t> fork_join;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+extern "C" {
+
+emagpie_status emagpie_group_workspace_size(int32_t n_inst, const emagpie_ctx* ctxs, size_t* bytes) {
+  if (!bytes) return fail(EMAGPIE_E_ARG, "null output");
+  GroupLayout G;
+  emagpie_status st = plan_group(n_inst, ctxs, &G);
+  if (st != EMAGPIE_OK) return st;
+  *bytes = G.total;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_group_destroy(emagpie_group g) {
+  if (!g) return EMAGPIE_OK;
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (hipEvent_t e : g->fork_join) (void)hipEventDestroy(e);
+  for (hipStream_t s : g->streams) (void)hipStreamDestroy(s);
+  for (int i = 0; i < 2; ++i) {
+    if (g->pin_ev[i]) {
+      (void)hipEventSynchronize(g->pin_ev[i]);
+      (void)hipEventDestroy(g->pin_ev[i]);
+    }
+    if (g->pinned[i]) (void)hipHostFree(g->pinned[i]);
+  }
+  delete g;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_group_create(emagpie_group* out, int32_t n_inst, const emagpie_ctx* ctxs,
+                                    void* workspace_dev, size_t workspace_bytes, void* stream) {
+  if (!out) return fail(EMAGPIE_E_ARG, "null group output");
+  *out = nullptr;
+  GroupLayout G;
+  emagpie_status st = plan_group(n_inst, ctxs, &G);
+  if (st != EMAGPIE_OK) return st;
+  if (!workspace_dev || (reinterpret_cast<uintptr_t>(workspace_dev) & 255))
+    return fail(EMAGPIE_E_WORKSPACE, "group workspace missing or not 256-byte aligned");
+  if (workspace_bytes < G.total)
+    return fail(EMAGPIE_E_WORKSPACE, "group workspace too small: need " + std::to_string(G.total) +
+                                         " bytes, got " + std::to_string(workspace_bytes));
+  auto* g = new emagpie_group_s();
+  g->n = n_inst;
+  g->ctx.assign(ctxs, ctxs + n_inst);
+  g->lay = G;
+  g->ws = static_cast<uint8_t*>(workspace_dev);
+  g->args_dev = reinterpret_cast<emg::StepArgs*>(g->ws + G.args);
+  g->slots_dev = reinterpret_cast<int4*>(g->ws + G.slots);
+  g->work_dev = reinterpret_cast<int2*>(g->ws + G.work);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto bad = [&](hipError_t e, const char* what) {
+    fail(EMAGPIE_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    emagpie_group_destroy(g);
+    return EMAGPIE_E_HIP;
+  };
+  hipError_t e;
+  if (!G.work_host.empty() &&
+      (e = hipMemcpyAsync(g->work_dev, G.work_host.data(), G.work_host.size() * sizeof(int2),
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return bad(e, "upload work lists");
+  size_t nslots = 0;
+  for (auto c : g->ctx) nslots += (size_t)c->cfg.n_pos;
+  for (int i = 0; i < 2; ++i) {
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&g->pinned[i]), sizeof(int4) * nslots,
+                           hipHostMallocDefault)) != hipSuccess)
+      return bad(e, "pinned scan-order buffer");
+    if ((e = hipEventCreateWithFlags(&g->pin_ev[i], hipEventDisableTiming)) != hipSuccess)
+      return bad(e, "event");
+  }
+  g->streams.resize(1 + G.classes.size());
+  for (auto& st2 : g->streams)
+    if ((e = hipStreamCreateWithFlags(&st2, hipStreamNonBlocking)) != hipSuccess)
+      return bad(e, "capture stream");
+  g->fork_join.resize(1 + G.classes.size());
+  for (auto& ev : g->fork_join)
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+      return bad(e, "event");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return bad(e, "synchronise");
+  *out = g;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_group_epoch(emagpie_group g, void* const* obj_devs, void* const* probe_devs,
+                                   int64_t epoch, double* sampled_misfit_dev, void* stream) {
+  if (!g || !obj_devs || !probe_devs) return fail(EMAGPIE_E_ARG, "null argument");
+  for (int i = 0; i < g->n; ++i)
+    if (!obj_devs[i] || !probe_devs[i]) return fail(EMAGPIE_E_ARG, "null object or probe in group");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = g->n, J = g->lay.steps;
+  // argument records (rebuilt only when the state buffers change)
+  bool same = g->args_valid && g->a_sampled == sampled_misfit_dev;
+  for (int i = 0; same && i < n; ++i) same = g->a_obj[i] == obj_devs[i] && g->a_probe[i] == probe_devs[i];
+  if (!same) {
+    g->args_host.assign((size_t)J * n, emg::StepArgs{});
+    for (int j = 0; j < J; ++j)
+      for (int i = 0; i < n; ++i) {
+        emagpie_ctx c = g->ctx[i];
+        emg::StepArgs a = base_args(c, obj_devs[i], probe_devs[i]);
+        const int B = c->cfg.minibatch, N = c->cfg.n_pos;
+        a.slot = g->slots_dev + g->lay.slot_off[i] + (size_t)std::min(j * B, N);
+        a.b = std::max(0, std::min(B, N - j * B));
+        a.sampled = sampled_misfit_dev ? sampled_misfit_dev + i : nullptr;
+        g->args_host[(size_t)j * n + i] = a;
+      }
+    EMG_HIP(hipMemcpyAsync(g->args_dev, g->args_host.data(), g->args_host.size() * sizeof(emg::StepArgs),
+                           hipMemcpyHostToDevice, s));
+    g->a_obj.assign(obj_devs, obj_devs + n);
+    g->a_probe.assign(probe_devs, probe_devs + n);
+    g->a_sampled = sampled_misfit_dev;
+    g->args_valid = true;
+  }
+  // scan orders of every instance for this epoch, one upload
+  const int ps = g->pin_slot;
+  g->pin_slot ^= 1;
+  EMG_HIP(hipEventSynchronize(g->pin_ev[ps]));
+  int4* dst = g->pinned[ps];
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    emagpie_ctx c = g->ctx[i];
+    const int N = c->cfg.n_pos;
+    g->perm_host.resize(N);
+    fisher_yates(c->cfg.seed, epoch, N, g->perm_host.data());
+    int4* d = dst + g->lay.slot_off[i];
+    for (int j = 0; j < N; ++j) {
+      const int k = g->perm_host[j];
+      d[j] = make_int4(k, c->pos_host[2 * k], c->pos_host[2 * k + 1], 0);
+    }
+    total += N;
+  }
+  EMG_HIP(hipMemcpyAsync(g->slots_dev, dst, total * sizeof(int4), hipMemcpyHostToDevice, s));
+  EMG_HIP(hipEventRecord(g->pin_ev[ps], s));
+  if (sampled_misfit_dev) EMG_HIP(emg::launch_zero_doubles(sampled_misfit_dev, n, s));
+  if (!g->gexec) {
+    // capture once: one chain of (patch, finalize) launches per probe-size class,
+    // the chains as parallel branches between a fork and a join
+    hipStream_t s0 = g->streams[0];
+    EMG_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipEventRecord(g->fork_join[0], s0);
+    for (size_t c = 0; ce == hipSuccess && c < g->lay.classes.size(); ++c) {
+      const GroupClass& k = g->lay.classes[c];
+      hipStream_t sc = g->streams[1 + c];
+      ce = hipStreamWaitEvent(sc, g->fork_join[0], 0);
+      for (int j = 0; ce == hipSuccess && j < J; ++j) {
+        if (k.patch_n[j] > 0)
+          ce = emg::launch_patch_step_multi(k.m, k.L, g->args_dev, g->work_dev + k.patch_off[j],
+                                            k.patch_n[j], sc);
+        if (ce == hipSuccess && k.fin_n[j] > 0)
+          ce = emg::launch_finalize_multi(k.m, g->args_dev, g->work_dev + k.fin_off[j], k.fin_n[j], sc);
+      }
+      if (ce == hipSuccess) ce = hipEventRecord(g->fork_join[1 + c], sc);
+      if (ce == hipSuccess) ce = hipStreamWaitEvent(s0, g->fork_join[1 + c], 0);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(s0, &graph);
+    if (ce != hipSuccess || ee != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(EMAGPIE_E_HIP, std::string("group capture: ") +
+                                     hipGetErrorString(ce != hipSuccess ? ce : ee));
+    }
+    g->graph = graph;
+    EMG_HIP(hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0));
+  }
+  EMG_HIP(hipGraphLaunch(g->gexec, s));
+  return EMAGPIE_OK;
+}
+
+}  // extern "C"

@@ -507,6 +507,27 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_patch_step(StepArgs a) {
 
 constexpr int kFinNT = 256;
 
+// ---------------------------------------------------------------------------
+// many independent reconstructions in one launch: block b serves work item
+// work[b] = (instance argument record, slot or finalize item); every
+// instance keeps its own state, data and workspace, so the arithmetic is the
+// single-instance arithmetic
+// ---------------------------------------------------------------------------
+template <int M, int L>
+__global__ __launch_bounds__(Plan<M>::NT) void k_patch_step_multi(const StepArgs* args,
+                                                                  const int2* work) {
+  __shared__ cx<float> A[M * lds_stride<M>()];
+  __shared__ cx<float> tws[M];
+  __shared__ float redf[32];
+  __shared__ double redd[16];
+  const int tid = threadIdx.x;
+  const int2 w = work[blockIdx.x];
+  const StepArgs a = args[w.x];
+  stage_twiddles<M>(a.tw, tws, tid);
+  __syncthreads();
+  patch_step<M, L>(a, w.y, A, tws, redf, redd, tid);
+}
+
 template <int M>
 __global__ __launch_bounds__(kFinNT) void k_finalize(StepArgs a, int ntiles) {
   __shared__ FinLds L;
@@ -514,6 +535,19 @@ __global__ __launch_bounds__(kFinNT) void k_finalize(StepArgs a, int ntiles) {
   load_slot_positions<M, kFinNT>(a, L, tid);
   __syncthreads();
   finalize_item<M, kFinNT>(a, blockIdx.x, ntiles, L, tid);
+}
+
+template <int M>
+__global__ __launch_bounds__(kFinNT) void k_finalize_multi(const StepArgs* args, const int2* work) {
+  __shared__ FinLds L;
+  const int tid = threadIdx.x;
+  const int2 w = work[blockIdx.x];
+  const StepArgs a = args[w.x];
+  int ntiles;
+  finalize_items<M, kFinNT>(a.n, &ntiles);
+  load_slot_positions<M, kFinNT>(a, L, tid);
+  __syncthreads();
+  finalize_item<M, kFinNT>(a, w.y, ntiles, L, tid);
 }
 
 // Grid-wide barrier for the persistent kernel (all workgroups co-resident by
@@ -931,6 +965,37 @@ static hipError_t finalize_l(const StepArgs& a, hipStream_t s, hipEvent_t e0, hi
 }
 hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   EMG_DISPATCH_M(m, finalize_l, a, s, e0, e1);
+}
+
+template <int M, int L>
+static hipError_t patch_multi_l(const StepArgs* args, const int2* work, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_patch_step_multi<M, L>), dim3(blocks), dim3(Plan<M>::NT), 0, s, args, work);
+  return hipGetLastError();
+}
+hipError_t launch_patch_step_multi(int m, int L, const StepArgs* args, const int2* work, int blocks,
+                                   hipStream_t s) {
+  EMG_DISPATCH_ML(m, L, patch_multi_l, args, work, blocks, s);
+}
+
+template <int M>
+static hipError_t finalize_multi_l(const StepArgs* args, const int2* work, int blocks,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_multi<M>, dim3(blocks), dim3(kFinNT), 0, s, args, work);
+  return hipGetLastError();
+}
+hipError_t launch_finalize_multi(int m, const StepArgs* args, const int2* work, int blocks,
+                                 hipStream_t s) {
+  EMG_DISPATCH_M(m, finalize_multi_l, args, work, blocks, s);
+}
+
+hipError_t finalize_item_count(int m, int n, int* items) {
+  int ntiles = 0;
+  switch (m) {
+    case 32: *items = finalize_items<32, kFinNT>(n, &ntiles); return hipSuccess;
+    case 64: *items = finalize_items<64, kFinNT>(n, &ntiles); return hipSuccess;
+    case 128: *items = finalize_items<128, kFinNT>(n, &ntiles); return hipSuccess;
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int M, int L>

@@ -42,6 +42,15 @@ hipError_t launch_patch_step(int m, int L, const StepArgs& a, hipStream_t s,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
+// Many instances per launch: block b runs work[b] = (record in args, slot) for
+// the patch stage, or (record in args, finalize item) for the finalize.
+hipError_t launch_patch_step_multi(int m, int L, const StepArgs* args, const int2* work, int blocks,
+                                   hipStream_t s);
+hipError_t launch_finalize_multi(int m, const StepArgs* args, const int2* work, int blocks,
+                                 hipStream_t s);
+// number of finalize work items (object tiles + probe units) for an n x n object
+hipError_t finalize_item_count(int m, int n, int* items);
+
 // plain path: the six patch-stage kernels (finalize is launched separately)
 hipError_t launch_plain_step(int m, int L, const StepArgs& a, hipStream_t s);
 

@@ -29,6 +29,8 @@ EXPORTS = [
     "emagpie_normalize_probe", "emagpie_step_minibatch", "emagpie_epoch", "emagpie_mg_cycle",
     "emagpie_misfit", "emagpie_grad", "emagpie_permutation", "emagpie_last_error",
     "emagpie_version", "emagpie_profile_enable", "emagpie_profile_read",
+    "emagpie_group_workspace_size", "emagpie_group_create", "emagpie_group_epoch",
+    "emagpie_group_destroy",
 ]
 
 
@@ -77,6 +79,10 @@ def lib() -> ctypes.CDLL:
         "emagpie_permutation": [u64, i64, i32, vp],
         "emagpie_profile_enable": [vp, i32],
         "emagpie_profile_read": [vp, vp, vp],
+        "emagpie_group_workspace_size": [i32, vp, ctypes.POINTER(sz)],
+        "emagpie_group_create": [ctypes.POINTER(vp), i32, vp, vp, sz, vp],
+        "emagpie_group_epoch": [vp, vp, vp, i64, vp, vp],
+        "emagpie_group_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -265,3 +271,47 @@ class AmplitudeMisfit(torch.autograd.Function):
     def backward(ctx, g):
         gobj, gprobe = ctx.saved_tensors
         return g.to(gobj.real.dtype) * gobj, g.to(gprobe.real.dtype) * gprobe, None
+
+
+class Group:
+    """Several independent reconstructions advanced together (one sweep each per call).
+
+    Every member keeps its own configuration, data and state; a group epoch gives
+    bitwise the same result as calling `Reconstruction.epoch` on each member.
+    """
+
+    def __init__(self, recs):
+        self.recs = list(recs)
+        n = len(self.recs)
+        self._ctxs = (ctypes.c_void_p * n)(*[r._ctx.value for r in self.recs])
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().emagpie_group_workspace_size(n, self._ctxs, ctypes.byref(nbytes)))
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self._ws.data_ptr() + 255) & ~255
+        self._g = ctypes.c_void_p(None)
+        _check(lib().emagpie_group_create(ctypes.byref(self._g), n, self._ctxs, ptr, nbytes.value,
+                                          _stream()))
+
+    def epoch(self, objs, probes, epoch: int, sampled: torch.Tensor | None = None):
+        n = len(self.recs)
+        if len(objs) != n or len(probes) != n:
+            raise ValueError("one object and one probe per member")
+        for r, o, q in zip(self.recs, objs, probes):
+            r._state(o, q)
+        if sampled is not None:
+            _expect(sampled, torch.float64, (n,), "sampled")
+        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in objs])
+        pp = (ctypes.c_void_p * n)(*[q.data_ptr() for q in probes])
+        _check(lib().emagpie_group_epoch(self._g, op, pp, int(epoch), _ptr(sampled), _stream()))
+
+    def close(self):
+        if getattr(self, "_g", None) is not None and self._g.value:
+            torch.cuda.current_stream().synchronize()
+            lib().emagpie_group_destroy(self._g)
+            self._g = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -185,13 +185,20 @@ def make_problem(name: str, *, n: int | None = None, m: int | None = None, scan=
         pos = raster_positions(n, m, scan[1], scan[2], scan[3], rng)
     else:
         pos = fermat_positions(n, m, scan[1])
-    d = simulate_intensities(probe, obj, pos)
+    d = None
     if photons is not None:
-        scale = photons / d.sum(axis=(1, 2)).mean()
+        # mean photon count per pattern: by Parseval sum |F psi|^2 = m^2 sum |psi|^2
+        energy = np.mean([np.sum(np.abs(probe * obj[r:r + m, c:c + m]) ** 2) for r, c in pos])
+        scale = photons / (m * m * energy)
         probe = probe * math.sqrt(scale)
-        d = d * scale
-        meas = rng.poisson(d).astype(np.float32)
+        meas = np.empty((pos.shape[0], m, m), dtype=np.float32)
+        for s0 in range(0, pos.shape[0], 512):
+            chunk = simulate_intensities(probe, obj, pos[s0:s0 + 512])
+            if keep_noiseless:
+                d = chunk if d is None else np.concatenate([d, chunk])
+            meas[s0:s0 + 512] = rng.poisson(chunk)
     else:
+        d = simulate_intensities(probe, obj, pos)
         meas = d.astype(np.float32)
     return Problem(
         name=name, n=n, m=m, positions=pos, intensities=meas,
@@ -208,3 +215,22 @@ def noise_percent(noisy: np.ndarray, clean: np.ndarray) -> float:
     """Noise% (amplitude) of Sec. 4.1: 100 sqrt(sum ||d - d~||^2 / sum ||d~||^2)."""
     diff = noisy.astype(np.float64) - clean
     return 100.0 * math.sqrt(float((diff * diff).sum()) / float((clean * clean).sum()))
+
+
+def make_c5(count: int = 16, seed: int = 1005) -> list:
+    """Uneven batched instances: object sides from {256, 384, 512, 768, 1024}, probe sides
+    from {64, 128}, 400-4096 jittered raster positions, Poisson photon counts log-uniform
+    in [1e5, 1e7], two multigrid levels, minibatch 64; instance j uses seed * 100 + j."""
+    out = []
+    for j in range(count):
+        rng = np.random.default_rng(seed * 100 + j)
+        n = int(rng.choice([256, 384, 512, 768, 1024]))
+        m = int(rng.choice([64, 128]))
+        npos = int(rng.integers(400, 4097))
+        side = max(2, int(round(math.sqrt(npos))))
+        step = max(1, (n - m - 4) // (side - 1))
+        photons = float(10.0 ** rng.uniform(5.0, 7.0))
+        p = make_problem(f"c5_{j}", n=n, m=m, scan=("raster", side, step, 1), photons=photons, B=64,
+                         L=2, alpha=0.05, seed=seed * 100 + j)
+        out.append(p)
+    return out
