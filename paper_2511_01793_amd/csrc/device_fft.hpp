@@ -38,6 +38,12 @@ template <typename T>
 __device__ __forceinline__ cx<T> mul(cx<T> a, cx<T> b) {
   return cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
+// complex product with two explicit fused multiply-adds (twiddles); explicit,
+// so it rounds the same way in every kernel that uses it
+template <typename T>
+__device__ __forceinline__ cx<T> mul_fma(cx<T> a, cx<T> b) {
+  return cx<T>{fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
+}
 // conj(a) * b
 template <typename T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
@@ -130,7 +136,7 @@ __device__ __forceinline__ void dft16(cx<T>* v, const cx<T>* tw) {
   for (int k = 0; k < 8; ++k) {
     cx<T> w = tw[k * (M / 16)];
     if (INV) w = conjg(w);
-    cx<T> t = mul(w, o[k]);
+    cx<T> t = mul_fma(w, o[k]);
     v[k] = add(e[k], t);
     v[k + 8] = sub(e[k], t);
   }
@@ -182,12 +188,12 @@ __device__ __forceinline__ void fft_pass(cx<T>* A, const cx<T>* tw, int tid) {
     }
     if (STRIDED && INV) {
 #pragma unroll
-      for (int j = 1; j < R; ++j) v[j] = mul(conjg(tw[g * j]), v[j]);
+      for (int j = 1; j < R; ++j) v[j] = mul_fma(conjg(tw[g * j]), v[j]);
     }
     dft_small<T, INV, R, M>(v, tw);
     if (STRIDED && !INV) {
 #pragma unroll
-      for (int j = 1; j < R; ++j) v[j] = mul(tw[g * j], v[j]);
+      for (int j = 1; j < R; ++j) v[j] = mul_fma(tw[g * j], v[j]);
     }
 #pragma unroll
     for (int j = 0; j < R; ++j) {

@@ -127,6 +127,15 @@ __device__ __forceinline__ cx<float> ld(const float2* p, size_t i) {
   return cx<float>{v.x, v.y};
 }
 __device__ __forceinline__ void st(float2* p, size_t i, cx<float> v) { p[i] = make_float2(v.re, v.im); }
+// two consecutive complex values at an even index of a 16-byte aligned array
+__device__ __forceinline__ void ld_pair(const float2* p, size_t i, cx<float>& a, cx<float>& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p + i);
+  a = cx<float>{v.x, v.y};
+  b = cx<float>{v.z, v.w};
+}
+__device__ __forceinline__ void st_pair(float2* p, size_t i, cx<float> a, cx<float> b) {
+  *reinterpret_cast<float4*>(p + i) = make_float4(a.re, a.im, b.re, b.im);
+}
 
 template <int M>
 struct Px {
@@ -140,6 +149,19 @@ struct Px {
   // gather to the numerators; several rounds reload them (register budget)
   static constexpr bool CACHE = ROUNDS == 1;
 };
+
+// Top-left pixel (r0, c0) of the thread's 2 x 2 block in round rd (c0 is even).
+template <int M>
+__device__ __forceinline__ void blk_origin(int tid, int rd, int& r0, int& c0) {
+  constexpr int QW = Px<M>::QW;
+  const int q = tid >> 2, sub = tid & 3;
+  r0 = 4 * (q / QW) + 2 * (sub >> 1);
+  c0 = 4 * (q % QW) + 2 * (sub & 1);
+  if constexpr (Px<M>::ROUNDS > 1) {
+    r0 += 64 * (rd >> 1);
+    c0 += 64 * (rd & 1);
+  }
+}
 
 // Pixel e of a thread: round e / 4, position (e / 2 % 2, e % 2) inside that
 // round's 2 x 2 block.  Four consecutive lanes own the four 2 x 2 blocks of one
@@ -157,32 +179,38 @@ __device__ __forceinline__ void pix_rc(int tid, int e, int& r, int& c) {
 }
 
 // ---------------------------------------------------------------------------
-// per-pixel surrogate algebra for one patch
-//   qf(e), zf(e), rf(e): probe, object window and revised exit wave at the
-//   thread's pixel e (see pix_rc); one round (2 x 2 block) at a time
+// per-pixel surrogate algebra for one patch, one 2 x 2 block (round) at a time
+//   load(rd, r0, c0, q, z, R) fills the probe, object window and revised exit
+//   wave of the block at (r0, c0); element 2 i + j is pixel (r0 + i, c0 + j)
 // ---------------------------------------------------------------------------
-template <int M, int L, class QF, class ZF, class RF>
-__device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, QF qf, ZF zf, RF rf,
+template <int M, int L, class LOAD>
+__device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, LOAD load,
                                              float qqmax, float zmax) {
   const size_t base = (size_t)s * M * M;
   const bool slot_den = a.pden_slot != nullptr;
 #pragma unroll
   for (int rd = 0; rd < Px<M>::ROUNDS; ++rd) {
-    // pass 1: block sums of g = conj(Q)(R - Q z), D, u, Q, |Q|^2
+    int r0, c0;
+    blk_origin<M>(tid, rd, r0, c0);
+    cx<float> q[4], zz[4], R[4];
+    load(rd, r0, c0, q, zz, R);
+    float q2[4], u[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      q2[e] = norm2(q[e]);
+      u[e] = a.alpha * (qqmax - q2[e]);
+    }
+    // block sums of g = conj(Q)(R - Q z), D, u, Q, |Q|^2
     cx<float> Gs{0.f, 0.f}, Qs{0.f, 0.f};
     float Ds = 0.f, Us = 0.f, Q2s = 0.f;
     if constexpr (L >= 2) {
 #pragma unroll
-      for (int e4 = 0; e4 < 4; ++e4) {
-        const int e = 4 * rd + e4;
-        const cx<float> q = qf(e), zz = zf(e), R = rf(e);
-        const float q2 = norm2(q);
-        const float u = a.alpha * (qqmax - q2);
-        Gs = add(Gs, cmulc(q, sub(R, mul(q, zz))));
-        Ds += q2 + u;
-        Us += u;
-        Qs = add(Qs, q);
-        Q2s += q2;
+      for (int e = 0; e < 4; ++e) {
+        Gs = add(Gs, cmulc(q[e], sub(R[e], mul(q[e], zz[e]))));
+        Ds += q2[e] + u[e];
+        Us += u[e];
+        Qs = add(Qs, q[e]);
+        Q2s += q2[e];
       }
     }
     // coarse correction of this 2 x 2 block: block-ratio form of the restricted
@@ -197,28 +225,35 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, 
       const cx<float> c2 = D2 > 0.f ? scale(G2, 1.f / D2) : cx<float>{0.f, 0.f};
       if (Ds > 0.f) cc = scale(add(Gs, scale(c2, Us)), 1.f / Ds);
     }
-    // pass 2: numerators and denominators
+    // numerators and denominators
+    cx<float> N[4], Mn[4];
+    float E[4], D[4];
 #pragma unroll
-    for (int e4 = 0; e4 < 4; ++e4) {
-      const int e = 4 * rd + e4;
-      int r, c;
-      pix_rc<M>(tid, e, r, c);
-      const cx<float> q = qf(e), zz = zf(e), R = rf(e);
-      const float q2 = norm2(q);
-      const float u = a.alpha * (qqmax - q2);
-      const float D = q2 + u;
-      const cx<float> zp = add(zz, cc);
-      const cx<float> N = add(cmulc(q, R), scale(zp, u));
-      const size_t o = base + (size_t)r * M + c;
+    for (int e = 0; e < 4; ++e) {
+      D[e] = q2[e] + u[e];
+      const cx<float> zp = add(zz[e], cc);
+      N[e] = add(cmulc(q[e], R[e]), scale(zp, u[e]));
       if (a.zplus) {
-        st(a.zplus, o, D > 0.f ? scale(N, 1.f / D) : zp);
+        N[e] = D[e] > 0.f ? scale(N[e], 1.f / D[e]) : zp;
       } else {
-        const float z2 = norm2(zz);
+        const float z2 = norm2(zz[e]);
         const float uz = a.alpha_z * (zmax - z2);
-        st(a.numer, o, N);
-        st(a.pnum, o, add(cmulc(zz, R), scale(q, uz)));
-        if (!slot_den) a.pden[o] = z2 + uz;
-        if (s == 0) a.Dbuf[r * M + c] = D;
+        Mn[e] = add(cmulc(zz[e], R[e]), scale(q[e], uz));
+        E[e] = z2 + uz;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const size_t o = base + (size_t)(r0 + i) * M + c0;
+      if (a.zplus) {
+        st_pair(a.zplus, o, N[2 * i], N[2 * i + 1]);
+      } else {
+        st_pair(a.numer, o, N[2 * i], N[2 * i + 1]);
+        st_pair(a.pnum, o, Mn[2 * i], Mn[2 * i + 1]);
+        if (!slot_den)
+          *reinterpret_cast<float2*>(a.pden + o) = make_float2(E[2 * i], E[2 * i + 1]);
+        if (s == 0)
+          *reinterpret_cast<float2*>(a.Dbuf + (r0 + i) * M + c0) = make_float2(D[2 * i], D[2 * i + 1]);
       }
     }
   }
@@ -227,13 +262,18 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, 
 }
 
 // modulus projection of one pixel in transform order: Psi' = a Psi/|Psi|
-// (a where Psi = 0), scaled by 1/m^2; returns (|Psi| - a)^2
+// (a where Psi = 0), scaled by 1/m^2; returns (|Psi| - a)^2.  The unit phase
+// factor Psi/|Psi| uses the hardware reciprocal square root (within one ulp)
+// instead of a correctly rounded square root and division.  |Psi|^2 below the
+// smallest normal float (|Psi| < 1.1e-19) counts as zero: theta := 0 there.
 template <int M>
 __device__ __forceinline__ float project_amp(cx<float>& P, float amp) {
-  const float mag = sqrtf(norm2(P));
-  const float diff = mag - amp;
-  const cx<float> o = mag > 0.f ? scale(P, amp / mag) : cx<float>{amp, 0.f};
-  P = scale(o, 1.f / float(M * M));
+  constexpr float kTiny = 1.17549435e-38f;  // FLT_MIN
+  const float p2 = norm2(P);
+  const bool live = p2 >= kTiny;
+  const float ir = __builtin_amdgcn_rsqf(live ? p2 : 1.f);
+  const float diff = live ? p2 * ir - amp : -amp;
+  P = live ? scale(P, amp * ir * (1.f / float(M * M))) : cx<float>{amp * (1.f / float(M * M)), 0.f};
   return diff * diff;
 }
 template <int M>
@@ -248,49 +288,52 @@ template <int M, int L>
 __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* A,
                                            const cx<float>* tws, float* redf, double* redd,
                                            int tid) {
-  constexpr int PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
+  constexpr int R = Px<M>::ROUNDS, NT = Px<M>::NT, LS = Px<M>::LS;
   const int4 sl = a.slot[s];
   const int k = sl.x;
   const size_t n = (size_t)a.n;
   const float2* zwin = a.obj + (size_t)sl.y * n + sl.z;
   const float* dk = a.dperm + (size_t)k * M * M;
-  auto lds = [&](int e) -> cx<float>& {
-    int r, c;
-    pix_rc<M>(tid, e, r, c);
-    return A[r * LS + c];
-  };
-  auto qld = [&](int e) {
-    int r, c;
-    pix_rc<M>(tid, e, r, c);
-    return ld(a.probe, (size_t)r * M + c);
-  };
-  auto zld = [&](int e) {
-    int r, c;
-    pix_rc<M>(tid, e, r, c);
-    return ld(zwin, (size_t)r * n + c);
-  };
-  // all global loads of the patch are issued here, before any dependent work
-  cx<float> qc[Px<M>::CACHE ? PX : 1], zc[Px<M>::CACHE ? PX : 1];
-  float amp[PX];
+  // every global load of the patch is issued here, before any dependent work:
+  // probe rows as 16-byte pairs, amplitude rows as 8-byte pairs, the object
+  // window (arbitrary alignment) per pixel
+  cx<float> qc[Px<M>::CACHE ? 4 : 1], zc[Px<M>::CACHE ? 4 : 1];
+  float amp[4 * R];
   float q2m = 0.f, z2m = 0.f;
 #pragma unroll
-  for (int e = 0; e < PX; ++e) {
-    int r, c;
-    pix_rc<M>(tid, e, r, c);
-    amp[e] = dk[r * M + c];
+  for (int rd = 0; rd < R; ++rd) {
+    int r0, c0;
+    blk_origin<M>(tid, rd, r0, c0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float2 dv = *reinterpret_cast<const float2*>(dk + (r0 + i) * M + c0);
+      amp[4 * rd + 2 * i] = dv.x;
+      amp[4 * rd + 2 * i + 1] = dv.y;
+    }
   }
 #pragma unroll
-  for (int e = 0; e < PX; ++e) amp[e] = sqrtf(fmaxf(amp[e], 0.f));
+  for (int e = 0; e < 4 * R; ++e) amp[e] = sqrtf(fmaxf(amp[e], 0.f));
 #pragma unroll
-  for (int e = 0; e < PX; ++e) {
-    const cx<float> q = qld(e), zz = zld(e);
-    if constexpr (Px<M>::CACHE) {
-      qc[e] = q;
-      zc[e] = zz;
+  for (int rd = 0; rd < R; ++rd) {
+    int r0, c0;
+    blk_origin<M>(tid, rd, r0, c0);
+    cx<float> q[4], zz[4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ld_pair(a.probe, (size_t)(r0 + i) * M + c0, q[2 * i], q[2 * i + 1]);
+      zz[2 * i] = ld(zwin, (size_t)(r0 + i) * n + c0);
+      zz[2 * i + 1] = ld(zwin, (size_t)(r0 + i) * n + c0 + 1);
     }
-    q2m = fmaxf(q2m, norm2(q));
-    z2m = fmaxf(z2m, norm2(zz));
-    lds(e) = mul(q, zz);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if constexpr (Px<M>::CACHE) {
+        qc[e] = q[e];
+        zc[e] = zz[e];
+      }
+      q2m = fmaxf(q2m, norm2(q[e]));
+      z2m = fmaxf(z2m, norm2(zz[e]));
+      A[(r0 + (e >> 1)) * LS + c0 + (e & 1)] = mul(q[e], zz[e]);
+    }
   }
   // wave maxima go to LDS now; the barriers of the transforms order them
   // before they are read in the per-pixel phase
@@ -299,20 +342,39 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
   fft2_forward<float, M>(A, tws, tid);
   double acc = 0.0;
 #pragma unroll
-  for (int e = 0; e < PX; ++e) acc += (double)project_amp<M>(lds(e), amp[e]);
+  for (int rd = 0; rd < R; ++rd) {
+    int r0, c0;
+    blk_origin<M>(tid, rd, r0, c0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      acc += (double)project_amp<M>(A[(r0 + (e >> 1)) * LS + c0 + (e & 1)], amp[4 * rd + e]);
+  }
   acc = wave_sum(acc);
   if ((tid & 63) == 0) redd[tid >> 6] = acc;
   __syncthreads();
   fft2_inverse<float, M>(A, tws, tid);
   float qqmax, zmax;
   lds_max2<NT>(redf, qqmax, zmax);
-  auto rf = [&](int e) { return lds(e); };
-  if constexpr (Px<M>::CACHE) {
-    pixel_update<M, L>(a, s, tid, [&](int e) { return qc[e]; }, [&](int e) { return zc[e]; }, rf,
-                       qqmax, zmax);
-  } else {
-    pixel_update<M, L>(a, s, tid, qld, zld, rf, qqmax, zmax);
-  }
+  pixel_update<M, L>(
+      a, s, tid,
+      [&](int rd, int r0, int c0, cx<float>* q, cx<float>* zz, cx<float>* Rv) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          if constexpr (Px<M>::CACHE) {
+            q[2 * i] = qc[2 * i];
+            q[2 * i + 1] = qc[2 * i + 1];
+            zz[2 * i] = zc[2 * i];
+            zz[2 * i + 1] = zc[2 * i + 1];
+          } else {
+            ld_pair(a.probe, (size_t)(r0 + i) * M + c0, q[2 * i], q[2 * i + 1]);
+            zz[2 * i] = ld(zwin, (size_t)(r0 + i) * n + c0);
+            zz[2 * i + 1] = ld(zwin, (size_t)(r0 + i) * n + c0 + 1);
+          }
+          Rv[2 * i] = A[(r0 + i) * LS + c0];
+          Rv[2 * i + 1] = A[(r0 + i) * LS + c0 + 1];
+        }
+      },
+      qqmax, zmax);
   if (tid == 0 && a.phi) a.phi[s] = lds_sum<NT>(redd) / (2.0 * M * M);
   __syncthreads();  // LDS is reused by the next slot of a persistent loop
 }
@@ -684,19 +746,18 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_numerators(StepArgs a) {
   const size_t n = (size_t)a.n;
   const float2* zwin = a.obj + (size_t)a.slot[s].y * n + a.slot[s].z;
   const float2* Rg = a.stack + (size_t)s * M * M;
-  auto pa = [&](int e) {
-    int r, c;
-    pix_rc<M>(tid, e, r, c);
-    return (size_t)r * M + c;
-  };
-  auto ga = [&](int e) {
-    int r, c;
-    pix_rc<M>(tid, e, r, c);
-    return (size_t)r * n + c;
-  };
-  pixel_update<M, L>(a, s, tid, [&](int e) { return ld(a.probe, pa(e)); },
-                     [&](int e) { return ld(zwin, ga(e)); }, [&](int e) { return ld(Rg, pa(e)); },
-                     a.qqmax[0], a.zmax[s]);
+  pixel_update<M, L>(
+      a, s, tid,
+      [&](int rd, int r0, int c0, cx<float>* q, cx<float>* zz, cx<float>* Rv) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          ld_pair(a.probe, (size_t)(r0 + i) * M + c0, q[2 * i], q[2 * i + 1]);
+          zz[2 * i] = ld(zwin, (size_t)(r0 + i) * n + c0);
+          zz[2 * i + 1] = ld(zwin, (size_t)(r0 + i) * n + c0 + 1);
+          ld_pair(Rg, (size_t)(r0 + i) * M + c0, Rv[2 * i], Rv[2 * i + 1]);
+        }
+      },
+      a.qqmax[0], a.zmax[s]);
 }
 
 // ---------------------------------------------------------------------------
