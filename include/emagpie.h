@@ -70,6 +70,9 @@ typedef struct {
   float alpha;          /* alpha of u_Q = alpha(||Q||_inf^2 - |Q|^2), >= 0 (Sec. 4)  */
   float alpha_z;        /* alpha_z of u_z; 1 = the ePIE probe step (Sec. 4)          */
   int32_t update_probe; /* 1 blind (object and probe); 0 object only                */
+  int32_t joint_step;   /* 1: geometric-mean, phase-aligned joint step of Eq. 6
+                           (eMAGPIE); 0: take z+ and Q+ directly, the rPIE update of
+                           Eq. 2 (with levels = 1)                                  */
   int32_t path;         /* EMAGPIE_PATH_*                                           */
   uint64_t seed;        /* scan-order generator seed                                */
 } emagpie_config;

@@ -348,7 +348,7 @@ def permutation(seed: int, epoch: int, n: int) -> np.ndarray:
 
 def run_epoch(Q, z, positions, a, *, seed: int, epoch: int, minibatch: int, alpha: float,
               alpha_z: float = 1.0, levels: int = 1, update_probe: bool = True,
-              perm: np.ndarray | None = None):
+              perm: np.ndarray | None = None, joint: bool = True):
     """One sweep (iteration j) over all scan positions in random order, in consecutive
     minibatches; the last one may be short (Sec. 3, stochastic strategy).  Returns (Q, z, sampled)."""
     n_pos = len(positions)
@@ -356,7 +356,8 @@ def run_epoch(Q, z, positions, a, *, seed: int, epoch: int, minibatch: int, alph
     sampled = 0.0
     for s in range(0, n_pos, minibatch):
         Q, z, info = step_minibatch(Q, z, positions, a, order[s:s + minibatch], alpha=alpha,
-                                    alpha_z=alpha_z, levels=levels, update_probe=update_probe)
+                                    alpha_z=alpha_z, levels=levels, update_probe=update_probe,
+                                    joint=joint)
         sampled += info["sampled_misfit"]
     return Q, z, sampled
 

@@ -112,6 +112,7 @@ emagpie_status check_config(const emagpie_config* c) {
   if (!(c->alpha_z >= 0.f) || !std::isfinite(c->alpha_z))
     return fail(EMAGPIE_E_ARG, "alpha_z must be finite and >= 0");
   if (c->update_probe != 0 && c->update_probe != 1) return fail(EMAGPIE_E_ARG, "update_probe must be 0 or 1");
+  if (c->joint_step != 0 && c->joint_step != 1) return fail(EMAGPIE_E_ARG, "joint_step must be 0 or 1");
   if (c->path < EMAGPIE_PATH_PLAIN || c->path > EMAGPIE_PATH_PERSISTENT)
     return fail(EMAGPIE_E_ARG, "unknown path");
   return EMAGPIE_OK;
@@ -169,6 +170,7 @@ emg::StepArgs base_args(emagpie_ctx c, void* obj, void* probe) {
   a.alpha = c->cfg.alpha;
   a.alpha_z = c->cfg.alpha_z;
   a.update_probe = c->cfg.update_probe;
+  a.joint = c->cfg.joint_step;
   a.tw = c->tw32;
   a.numer = c->numer;
   a.pnum = c->pnum;

@@ -485,8 +485,8 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
         const int y = ty + q / T, x = tx + q % T;
         if (accd[e] > 0.f && y < n && x < n) {
           const size_t o = (size_t)y * n + x;
-          const cx<float> z = ld(a.obj, o);
-          st(a.obj, o, aligned_sqrt(z, scale(accn[e], 1.f / accd[e])));
+          const cx<float> zp = scale(accn[e], 1.f / accd[e]);
+          st(a.obj, o, a.joint ? aligned_sqrt(ld(a.obj, o), zp) : zp);
         }
       }
     }
@@ -534,8 +534,8 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
       const cx<float> mt = add(m01, m23);
       const float et = e01 + e23;
       if (et > 0.f) {
-        const cx<float> q = ld(a.probe, r);
-        st(a.probe, r, aligned_sqrt(q, scale(mt, 1.f / et)));
+        const cx<float> qp = scale(mt, 1.f / et);
+        st(a.probe, r, a.joint ? aligned_sqrt(ld(a.probe, r), qp) : qp);
       }
     }
     if (item == ntiles && tid == 0 && a.sampled) {

@@ -20,6 +20,7 @@ struct StepArgs {
   int b;
   float alpha, alpha_z;
   int update_probe;
+  int joint;         // 1: Eq. 6 joint step; 0: z <- z+, Q <- Q+ (Eq. 2)
   const float2* tw;  // m twiddles exp(-2 pi i j / m)
   // per-slot products of the patch stage
   float2* numer;     // b x m^2 object numerators conj(Q) R + u z'

@@ -46,7 +46,8 @@ class Config(ctypes.Structure):
         ("n", ctypes.c_int32), ("m", ctypes.c_int32), ("n_pos", ctypes.c_int32),
         ("minibatch", ctypes.c_int32), ("levels", ctypes.c_int32),
         ("alpha", ctypes.c_float), ("alpha_z", ctypes.c_float),
-        ("update_probe", ctypes.c_int32), ("path", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("update_probe", ctypes.c_int32), ("joint_step", ctypes.c_int32), ("path", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -138,7 +139,8 @@ class Reconstruction:
 
     def __init__(self, positions, intensities: torch.Tensor, n: int, *, minibatch: int,
                  levels: int = 1, alpha: float = 0.05, alpha_z: float = 1.0,
-                 update_probe: bool = True, path: str = "graph", seed: int = 0):
+                 update_probe: bool = True, joint_step: bool = True, path: str = "graph",
+                 seed: int = 0):
         pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(-1, 2))
         if intensities.dim() != 3 or intensities.dtype != torch.float32 or not intensities.is_cuda:
             raise ValueError("intensities must be a (N, m, m) float32 CUDA tensor")
@@ -149,7 +151,8 @@ class Reconstruction:
         self.n, self.m, self.n_pos = int(n), int(m), int(N)
         self.cfg = Config(n=self.n, m=self.m, n_pos=self.n_pos, minibatch=int(minibatch),
                           levels=int(levels), alpha=float(alpha), alpha_z=float(alpha_z),
-                          update_probe=int(bool(update_probe)), path=PATHS[path],
+                          update_probe=int(bool(update_probe)), joint_step=int(bool(joint_step)),
+                          path=PATHS[path],
                           seed=int(seed) & ((1 << 64) - 1))
         nbytes = workspace_size(self.cfg)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=intensities.device)

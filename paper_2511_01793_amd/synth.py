@@ -41,6 +41,12 @@ __all__ = [
     "simulate_intensities",
     "make_problem",
     "CONFIGS",
+    "textured_object",
+    "zone_plate_probe",
+    "perturbed_initial_probe",
+    "overlap_positions",
+    "photon_scale_for_noise",
+    "make_protocol_problem",
 ]
 
 
@@ -234,3 +240,135 @@ def make_c5(count: int = 16, seed: int = 1005) -> list:
                          L=2, alpha=0.05, seed=seed * 100 + j)
         out.append(p)
     return out
+
+
+# --------------------------------------------------------------------------
+# Stand-ins for the inputs of the paper's synthetic experiments (Sec. 5.1)
+# --------------------------------------------------------------------------
+
+def textured_object(n: int, rng: np.random.Generator, n_blobs: int = 400) -> np.ndarray:
+    """Object with the value ranges of the paper's test object: |z*| in [0, 1] and arg z* in
+    [0, pi/2] (Sec. 5.1), each channel a min-max normalised sum of n_blobs Gaussian blobs of
+    width U[n/256, n/24] (finer texture than make_object, standing in for natural images)."""
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+
+    def channel() -> np.ndarray:
+        f = np.zeros((n, n))
+        for _ in range(n_blobs):
+            cy, cx = rng.uniform(0, n, size=2)
+            s = rng.uniform(n / 256.0, n / 24.0)
+            w = rng.uniform(-1.0, 1.0)
+            r0, r1 = int(max(0, cy - 5 * s)), int(min(n, cy + 5 * s + 1))
+            c0, c1 = int(max(0, cx - 5 * s)), int(min(n, cx + 5 * s + 1))
+            f[r0:r1, c0:c1] += w * np.exp(-((yy[r0:r1, c0:c1] - cy) ** 2
+                                            + (xx[r0:r1, c0:c1] - cx) ** 2) / (2.0 * s * s))
+        f -= f.min()
+        mx = f.max()
+        return f / mx if mx > 0 else f
+
+    mag = channel()
+    ph = channel()
+    return mag * np.exp(1j * (np.pi / 2.0) * ph)
+
+
+def zone_plate_probe(m: int, outer: float = 0.1875, stop: float = 0.4,
+                     spot: float = 0.25) -> np.ndarray:
+    """Defocused Fresnel-zone-plate illumination (stand-in for the simulated FZP of Sec. 5.1).
+
+    A zone plate with a central stop passes an annulus of spatial frequencies,
+    stop * outer * m <= |k| <= outer * m (cycles per window).  Out of focus, each frequency
+    picks up the quadratic phase beta |k|^2; beta is chosen so that the geometric shadow of the
+    outer zone has radius spot * m pixels.  The result has ring-structured magnitude, very low
+    magnitude outside the central disc and concentric phase bands.  Scaled to max |Q| = 1,
+    centred on the window centre.
+    """
+    k = np.fft.fftfreq(m) * m
+    ky, kx = np.meshgrid(k, k, indexing="ij")
+    rho = np.sqrt(kx * kx + ky * ky)
+    r_out = outer * m
+    beta = np.pi * spot / r_out
+    # annulus with its edges softened over one frequency sample to limit ringing
+    pupil = np.clip(np.minimum(r_out + 0.5 - rho, rho - stop * r_out + 0.5), 0.0, 1.0)
+    field = np.fft.fftshift(np.fft.ifft2(pupil * np.exp(1j * beta * rho * rho)))
+    # fftshift puts the spot centre at pixel m/2; the windows used here are even-sized
+    return field / np.abs(field).max()
+
+
+def perturbed_initial_probe(probe_true: np.ndarray, rng: np.random.Generator, *,
+                            sigma_amp: float = 2.0, ramp: float = 7.0, defocus: float = 0.6,
+                            astig: float = 0.2, noise: float = 0.01) -> np.ndarray:
+    """Initial probe from the ground truth (Sec. 5.1): Fourier-domain Gaussian blur of |Q*|,
+    a random linear phase ramp of total size `ramp` rad across the window, defocus and
+    astigmatism terms, plus complex noise of relative amplitude `noise`.
+
+    Coordinates x (columns) and y (rows) run over [-1, 1] across the window; the ramp
+    (a_x, a_y) = (ramp / 2) (cos b, sin b) with b ~ U[0, 2 pi) changes the phase by `ramp` rad
+    from edge to edge along its direction; the noise is circular Gaussian with standard
+    deviation noise * rms|Q0|.
+    """
+    m = probe_true.shape[0]
+    k = np.fft.fftfreq(m)
+    ky, kx = np.meshgrid(k, k, indexing="ij")
+    # transfer function of a spatial Gaussian of standard deviation sigma_amp pixels
+    H = np.exp(-2.0 * np.pi ** 2 * sigma_amp ** 2 * (kx * kx + ky * ky))
+    mag = np.real(np.fft.ifft2(np.fft.fft2(np.abs(probe_true)) * H))
+    mag = np.maximum(mag, 0.0)
+    t = np.linspace(-1.0, 1.0, m)
+    y, x = np.meshgrid(t, t, indexing="ij")
+    b = rng.uniform(0.0, 2.0 * np.pi)
+    ax, ay = 0.5 * ramp * np.cos(b), 0.5 * ramp * np.sin(b)
+    phase = ax * x + ay * y + defocus * (x * x + y * y) + astig * (x * x - y * y)
+    q0 = mag * np.exp(1j * phase)
+    rms = math.sqrt(float(np.mean(np.abs(q0) ** 2)))
+    q0 = q0 + noise * rms * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))) / math.sqrt(2.0)
+    return q0
+
+
+def overlap_positions(n: int, m: int, overlap: float, rng: np.random.Generator,
+                      jitter: int = 2) -> np.ndarray:
+    """Raster whose neighbours are shifted by m (1 - overlap) pixels (the overlap ratio of
+    Sec. 2.1: 50% = half a probe width), as many per side as fit in [0, n - m], centred,
+    with integer jitter in {-jitter..jitter} against raster artefacts."""
+    step = max(1, int(round(m * (1.0 - overlap))))
+    side = (n - m) // step + 1
+    return raster_positions(n, m, side, step, jitter, rng)
+
+
+def photon_scale_for_noise(clean: np.ndarray, percent: float) -> float:
+    """Factor s such that Poisson counts of s * clean have expected Noise% (Sec. 5.1) equal to
+    `percent`: the Poisson variance equals the mean, so E sum n^2 = s sum f and
+    Noise%^2 / 100^2 = sum f / (s sum f^2)."""
+    c = np.asarray(clean, np.float64)
+    return float(c.sum() / ((c * c).sum() * (percent / 100.0) ** 2))
+
+
+def make_protocol_problem(*, overlap: float, noise_percent: float | None = None, n: int = 512,
+                          m: int = 128, alpha: float | None = None, B: int = 1, L: int = 1,
+                          seed: int = 2025) -> Problem:
+    """Synthetic analogue of the paper's overlap (Sec. 5.2) and noise (Sec. 5.3) studies.
+
+    Object from textured_object, zone-plate probe, overlap raster, the perturbed initial probe
+    of Sec. 5.1; noiseless data, or Poisson data at a target Noise%.  alpha defaults to the
+    paper's choice (0.05 at 50% overlap and for the noise study, 0.01 at 75% / 87.5%).
+    """
+    rng = np.random.default_rng(seed)
+    obj = textured_object(n, rng)
+    probe = zone_plate_probe(m)
+    pos = overlap_positions(n, m, overlap, rng)
+    clean = simulate_intensities(probe, obj, pos)
+    if noise_percent is None:
+        meas = clean.astype(np.float32)
+    else:
+        s = photon_scale_for_noise(clean, noise_percent)
+        probe = probe * math.sqrt(s)
+        clean = clean * s
+        meas = rng.poisson(clean).astype(np.float32)
+    if alpha is None:
+        alpha = 0.05 if (noise_percent is not None or overlap <= 0.5 + 1e-9) else 0.01
+    q0 = perturbed_initial_probe(probe, rng)
+    return Problem(
+        name=f"protocol_o{overlap:g}_n{noise_percent}", n=n, m=m, positions=pos, intensities=meas,
+        probe_true=probe, object_true=obj, probe_init=q0.astype(np.complex64),
+        object_init=np.ones((n, n), dtype=np.complex64), minibatch=B, levels=L, alpha=alpha,
+        alpha_z=1.0, epochs=0, seed=seed, photons=None, noiseless=clean,
+    )

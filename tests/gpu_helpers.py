@@ -26,7 +26,8 @@ def problem(name="tiny", **kw):
     return synth.make_problem(name, **kw)
 
 
-def make_rec(p, path="fused", levels=None, minibatch=None, alpha=None, update_probe=True, seed=3):
+def make_rec(p, path="fused", levels=None, minibatch=None, alpha=None, update_probe=True, seed=3,
+             joint_step=True):
     import torch
     import paper_2511_01793_amd.emagpie as E
     d = torch.from_numpy(p.intensities).cuda()
@@ -34,7 +35,7 @@ def make_rec(p, path="fused", levels=None, minibatch=None, alpha=None, update_pr
                            minibatch=p.minibatch if minibatch is None else minibatch,
                            levels=p.levels if levels is None else levels,
                            alpha=p.alpha if alpha is None else alpha, alpha_z=p.alpha_z,
-                           update_probe=update_probe, path=path, seed=seed)
+                           update_probe=update_probe, joint_step=joint_step, path=path, seed=seed)
     return rec
 
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def cfg(**kw):
     base = dict(n=128, m=32, n_pos=100, minibatch=10, levels=1, alpha=0.01, alpha_z=1.0,
-                update_probe=1, path=0, seed=0)
+                update_probe=1, joint_step=1, path=0, seed=0)
     base.update(kw)
     return E.Config(**base)
 
@@ -42,7 +42,7 @@ def cfg(**kw):
     (dict(levels=0), "E_SHAPE"), (dict(levels=4), "E_SHAPE"), (dict(minibatch=0), "E_SHAPE"),
     (dict(minibatch=2048), "E_SHAPE"), (dict(n_pos=0), "E_SHAPE"),
     (dict(alpha=float("nan")), "E_ARG"), (dict(alpha=-1.0), "E_ARG"), (dict(alpha_z=float("inf")), "E_ARG"),
-    (dict(path=9), "E_ARG"), (dict(update_probe=2), "E_ARG"),
+    (dict(path=9), "E_ARG"), (dict(update_probe=2), "E_ARG"), (dict(joint_step=3), "E_ARG"),
 ])
 def test_config_validation(bad, status):
     with pytest.raises(E.EmagpieError) as ei:
