@@ -55,8 +55,12 @@ enum {
   EMAGPIE_PATH_PLAIN = 0,  /* one launch per stage, HBM intermediates          */
   EMAGPIE_PATH_FUSED = 1,  /* fused per-patch kernel + finalize kernel         */
   EMAGPIE_PATH_GRAPH = 2,  /* FUSED launches replayed from a captured hipGraph */
-  EMAGPIE_PATH_PERSISTENT = 3 /* one cooperative launch per epoch, grid barriers */
+  EMAGPIE_PATH_PERSISTENT = 3, /* one cooperative launch per epoch, grid barriers */
+  EMAGPIE_PATH_AUTO = 4  /* chosen at init by timing FUSED, GRAPH and PERSISTENT epochs */
 };
+
+/* fft_plan / finalize_shape value asking emagpie_init to choose by timing */
+enum { EMAGPIE_TUNE = -1 };
 
 enum { EMAGPIE_F32 = 0, EMAGPIE_F64 = 1 };
 
@@ -75,7 +79,33 @@ typedef struct {
                            Eq. 2 (with levels = 1)                                  */
   int32_t path;         /* EMAGPIE_PATH_*                                           */
   uint64_t seed;        /* scan-order generator seed                                */
+  int32_t fft_plan;     /* kernel shape of the patch stage: 0 .. count-1 (see
+                           emagpie_plan_describe; 0 is the default), or EMAGPIE_TUNE */
+  int32_t finalize_shape; /* finalize work-item shape 0..3 (0 default), or EMAGPIE_TUNE */
+  const char* tune_cache; /* NULL, or a file of autotuning results (JSON lines) that
+                           emagpie_init reads before timing and appends to after  */
 } emagpie_config;
+
+/*
+ * Kernel plan of a context.  The FFT plan fixes the radix split m = r1 * r2 of
+ * the LDS transforms and the threads per patch; the finalize shape fixes the
+ * threads per work item and the object tile side.  Plans that share (r1, r2)
+ * give bitwise-identical results; other splits round the same transform
+ * differently (and lay the intensities out in their own order).  Finalize
+ * shapes never change results.
+ */
+typedef struct {
+  int32_t fft_plan, r1, r2, threads;
+  int32_t finalize_shape, fin_threads, fin_tile;
+  int32_t path;          /* EMAGPIE_PATH_* in use (never AUTO)                       */
+  int32_t tuned;         /* 0 fixed by the config, 1 timed at init, 2 from tune_cache */
+  int32_t n_fft_plans;   /* candidates timed (0 if the FFT plan was not timed)      */
+  float fft_us[4];       /* median patch-stage kernel time per candidate, us        */
+  int32_t n_fin_shapes;  /* candidates timed (0 if the shape was not timed)         */
+  float fin_us[4];       /* median finalize kernel time per candidate, us           */
+  float path_ms[4];      /* median epoch time per path (index EMAGPIE_PATH_*), ms; -1
+                            where not timed (PLAIN is never a candidate)            */
+} emagpie_plan;
 
 /* Bytes of device workspace a context with this configuration needs. */
 emagpie_status emagpie_workspace_size(const emagpie_config* cfg, size_t* bytes);
@@ -90,6 +120,15 @@ emagpie_status emagpie_workspace_size(const emagpie_config* cfg, size_t* bytes);
  * and at least emagpie_workspace_size() bytes; it stays owned by the caller
  * and must outlive the context.  This call synchronises the stream: it
  * returns EMAGPIE_E_DATA if any intensity is NaN or Inf.
+ *
+ * Autotuning (fft_plan or finalize_shape = EMAGPIE_TUNE, or path =
+ * EMAGPIE_PATH_AUTO): unless tune_cache holds a result for this device and
+ * problem shape, init times the candidates on the given intensities and
+ * positions with a scratch state held in the workspace: each FFT plan's
+ * patch-stage kernel and each finalize shape over minibatches of the epoch-0
+ * scan order, then whole epochs of each path; it keeps the fastest and appends
+ * it to tune_cache.  The caller's buffers are not touched.  A tune_cache that
+ * cannot be read or written is ignored.
  */
 emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
                             const int32_t* positions_host, const float* intensities_dev,
@@ -209,6 +248,20 @@ emagpie_status emagpie_group_create(emagpie_group* out, int32_t n_inst, const em
 emagpie_status emagpie_group_epoch(emagpie_group g, void* const* obj_devs, void* const* probe_devs,
                                    int64_t epoch, double* sampled_misfit_dev, void* stream);
 emagpie_status emagpie_group_destroy(emagpie_group g);
+
+/*
+ * The plan a context runs with (after any autotuning at init).  Host only.
+ */
+emagpie_status emagpie_plan_get(emagpie_ctx ctx, emagpie_plan* out_host);
+
+/*
+ * Describe FFT plan fft_plan and finalize shape finalize_shape for probe side
+ * m without a context or a GPU (fills the shape fields of out_host; the
+ * timing fields are zero).  EMAGPIE_E_ARG if either does not exist for m;
+ * *count_host (nullable) receives the number of FFT plans for m.
+ */
+emagpie_status emagpie_plan_describe(int32_t m, int32_t fft_plan, int32_t finalize_shape,
+                                     emagpie_plan* out_host, int32_t* count_host);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* emagpie_last_error(void);

@@ -2,13 +2,16 @@
 // strategies (plain, fused, captured hipGraph, persistent cooperative).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "../../include/emagpie.h"
 #include "launch.hpp"
+#include "plans.hpp"
 
 namespace {
 
@@ -56,9 +59,13 @@ struct Region {
   size_t off, bytes;
 };
 
+bool wants_tuning(const emagpie_config& c) {
+  return c.fft_plan == EMAGPIE_TUNE || c.finalize_shape == EMAGPIE_TUNE || c.path == EMAGPIE_PATH_AUTO;
+}
+
 struct Layout {
   Region dperm, pos, slots, tw32, tw64, numer, pnum, pden, pden_slot, phi, stack, zmax, ubuf, Dbuf, scal,
-      bar, phi_all, gz, gq;
+      bar, phi_all, gz, gq, tune_obj, tune_probe;
   int grad_chunk;
   size_t total;
 };
@@ -95,6 +102,10 @@ Layout make_layout(const emagpie_config& c) {
   const size_t gel = c.m <= 64 ? 16 : 8;  // complex128 where the float64 gradient exists
   L.gz = take((size_t)L.grad_chunk * m2 * gel);
   L.gq = take((size_t)L.grad_chunk * m2 * gel);
+  // scratch state for autotuning at init (only when asked for)
+  const bool tune = wants_tuning(c);
+  L.tune_obj = take(tune ? (size_t)c.n * c.n * 8 : 0);
+  L.tune_probe = take(tune ? m2 * 8 : 0);
   L.total = cur;
   return L;
 }
@@ -113,16 +124,23 @@ emagpie_status check_config(const emagpie_config* c) {
     return fail(EMAGPIE_E_ARG, "alpha_z must be finite and >= 0");
   if (c->update_probe != 0 && c->update_probe != 1) return fail(EMAGPIE_E_ARG, "update_probe must be 0 or 1");
   if (c->joint_step != 0 && c->joint_step != 1) return fail(EMAGPIE_E_ARG, "joint_step must be 0 or 1");
-  if (c->path < EMAGPIE_PATH_PLAIN || c->path > EMAGPIE_PATH_PERSISTENT)
+  if (c->path < EMAGPIE_PATH_PLAIN || c->path > EMAGPIE_PATH_AUTO)
     return fail(EMAGPIE_E_ARG, "unknown path");
+  if (c->fft_plan != EMAGPIE_TUNE && (c->fft_plan < 0 || c->fft_plan >= emg::fft_plan_count(c->m)))
+    return fail(EMAGPIE_E_ARG, "fft_plan must be EMAGPIE_TUNE or in [0, " +
+                                   std::to_string(emg::fft_plan_count(c->m)) + ") for this m");
+  if (c->finalize_shape != EMAGPIE_TUNE && (c->finalize_shape < 0 || c->finalize_shape >= emg::kFinShapes))
+    return fail(EMAGPIE_E_ARG, "finalize_shape must be EMAGPIE_TUNE or in [0, 4)");
   return EMAGPIE_OK;
 }
 
 }  // namespace
 
 struct emagpie_ctx_s {
-  emagpie_config cfg;
+  emagpie_config cfg;  // path, fft_plan and finalize_shape hold the resolved choice
   Layout lay;
+  int layout_plan = 0;  // FFT plan whose transform order dperm holds
+  emagpie_plan plan{};
   uint8_t* ws;
   float* dperm;
   int2* pos;
@@ -215,13 +233,13 @@ emagpie_status enqueue_minibatch(emagpie_ctx c, const emg::StepArgs& a, bool pla
   if (plain) {
     // six kernels: the pair brackets the group on the stream
     if (e0) EMG_HIP(hipEventRecord(e0, s));
-    EMG_HIP(emg::launch_plain_step(m, L, a, s));
+    EMG_HIP(emg::launch_plain_step(m, c->cfg.fft_plan, L, a, s));
     if (e1) EMG_HIP(hipEventRecord(e1, s));
   } else {
-    EMG_HIP(emg::launch_patch_step(m, L, a, s, e0, e1));
+    EMG_HIP(emg::launch_patch_step(m, c->cfg.fft_plan, L, a, s, e0, e1));
   }
   EMG_OK(take_pair(c, 1, instrument, &e0, &e1));
-  EMG_HIP(emg::launch_finalize(m, a, s, e0, e1));
+  EMG_HIP(emg::launch_finalize(m, c->cfg.finalize_shape, a, s, e0, e1));
   return EMAGPIE_OK;
 }
 
@@ -245,6 +263,243 @@ void drop_graph(emagpie_ctx c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   c->gexec = nullptr;
   c->graph = nullptr;
+}
+
+
+// ---------------------------------------------------------------------------
+// autotuning at init
+// ---------------------------------------------------------------------------
+void fill_plan_info(emagpie_ctx c, int tuned) {
+  emagpie_plan& p = c->plan;
+  p.fft_plan = c->cfg.fft_plan;
+  emg::fft_plan_desc(c->cfg.m, p.fft_plan, &p.r1, &p.r2, &p.threads);
+  p.finalize_shape = c->cfg.finalize_shape;
+  emg::fin_shape_desc(p.finalize_shape, &p.fin_threads, &p.fin_tile);
+  p.path = c->cfg.path;
+  p.tuned = tuned;
+  if (tuned == 0) {
+    p.n_fft_plans = p.n_fin_shapes = 0;
+    for (int i = 0; i < 4; ++i) p.fft_us[i] = p.fin_us[i] = p.path_ms[i] = -1.f;
+  }
+}
+
+std::string tune_key(emagpie_ctx c, const emagpie_config& req) {
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+  }
+  const emagpie_config& k = c->cfg;
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "%s cus=%d m=%d n=%d N=%d B=%d L=%d blind=%d joint=%d az1=%d plan=%d shape=%d path=%d",
+                arch.c_str(), c->num_cus, k.m, k.n, k.n_pos, k.minibatch, k.levels, k.update_probe,
+                k.joint_step, k.alpha_z == 1.0f ? 1 : 0, req.fft_plan, req.finalize_shape, req.path);
+  return buf;
+}
+
+bool json_int(const std::string& line, const char* name, int* out) {
+  const std::string pat = std::string("\"") + name + "\": ";
+  const size_t at = line.find(pat);
+  if (at == std::string::npos) return false;
+  char* end = nullptr;
+  const long v = std::strtol(line.c_str() + at + pat.size(), &end, 10);
+  if (end == line.c_str() + at + pat.size()) return false;
+  *out = (int)v;
+  return true;
+}
+
+// last line of the cache whose key matches; false if none (or unreadable)
+bool cache_lookup(const char* path, const std::string& key, int* v, int* f, int* p) {
+  if (!path) return false;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return false;
+  bool found = false;
+  const std::string kpat = "\"key\": \"" + key + "\"";
+  char buf[4096];
+  while (std::fgets(buf, sizeof buf, fp)) {
+    const std::string line(buf);
+    if (line.find(kpat) == std::string::npos) continue;
+    int a, b, q;
+    if (json_int(line, "fft_plan", &a) && json_int(line, "finalize_shape", &b) &&
+        json_int(line, "path", &q)) {
+      *v = a;
+      *f = b;
+      *p = q;
+      found = true;
+    }
+  }
+  std::fclose(fp);
+  return found;
+}
+
+void cache_append(const char* path, const std::string& key, const emagpie_plan& p) {
+  if (!path) return;
+  FILE* fp = std::fopen(path, "a");
+  if (!fp) return;
+  auto arr = [](const float* x, int n) {
+    std::string r = "[";
+    for (int i = 0; i < n; ++i) {
+      char b[32];
+      std::snprintf(b, sizeof b, "%s%.4g", i ? ", " : "", x[i]);
+      r += b;
+    }
+    return r + "]";
+  };
+  std::fprintf(fp,
+               "{\"key\": \"%s\", \"fft_plan\": %d, \"finalize_shape\": %d, \"path\": %d, "
+               "\"fft_us\": %s, \"fin_us\": %s, \"path_ms\": %s}\n",
+               key.c_str(), p.fft_plan, p.finalize_shape, p.path, arr(p.fft_us, 4).c_str(),
+               arr(p.fin_us, 4).c_str(), arr(p.path_ms, 4).c_str());
+  std::fclose(fp);
+}
+
+// Lay the intensities out in the transform order of FFT plan v (if the
+// current layout's radix split differs).
+emagpie_status relayout(emagpie_ctx c, int v, const float* intensities_dev, hipStream_t s) {
+  int r1a, r2a, nta, r1b, r2b, ntb;
+  emg::fft_plan_desc(c->cfg.m, c->layout_plan, &r1a, &r2a, &nta);
+  emg::fft_plan_desc(c->cfg.m, v, &r1b, &r2b, &ntb);
+  if (r1a != r1b || r2a != r2b) {
+    EMG_HIP(emg::launch_layout_intensities(c->cfg.m, v, intensities_dev, c->dperm, c->cfg.n_pos,
+                                           c->phi_all, c->scal_i + 3, s));
+  }
+  c->layout_plan = v;
+  return EMAGPIE_OK;
+}
+
+float median(std::vector<float> x) {
+  std::sort(x.begin(), x.end());
+  return x.empty() ? -1.f : x[x.size() / 2];
+}
+
+// Time `reps` launches made by enq(rep, e0, e1) (each brackets its timed kernel
+// with the events) after `warm` untimed ones; median milliseconds.
+template <class Enq>
+emagpie_status time_kernel(hipStream_t s, int warm, int reps, Enq enq, float* ms_out) {
+  std::vector<hipEvent_t> ev(2 * reps, nullptr);
+  emagpie_status st = EMAGPIE_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) st = fail(EMAGPIE_E_HIP, "tuner event");
+  for (int i = 0; st == EMAGPIE_OK && i < warm; ++i) st = enq(i, nullptr, nullptr);
+  for (int i = 0; st == EMAGPIE_OK && i < reps; ++i) st = enq(warm + i, ev[2 * i], ev[2 * i + 1]);
+  if (st == EMAGPIE_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(EMAGPIE_E_HIP, "tuner sync");
+  std::vector<float> ms;
+  for (int i = 0; st == EMAGPIE_OK && i < reps; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) != hipSuccess)
+      st = fail(EMAGPIE_E_HIP, "tuner timing");
+    ms.push_back(t);
+  }
+  (void)hipStreamSynchronize(s);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  *ms_out = median(ms);
+  return st;
+}
+
+emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* intensities_dev,
+                        hipStream_t s) {
+  const int m = c->cfg.m, N = c->cfg.n_pos, B = c->cfg.minibatch, L = c->cfg.levels;
+  const std::string key = tune_key(c, req);
+  int cv, cf, cp;
+  if (cache_lookup(req.tune_cache, key, &cv, &cf, &cp) && cv >= 0 && cv < emg::fft_plan_count(m) &&
+      cf >= 0 && cf < emg::kFinShapes && cp >= EMAGPIE_PATH_PLAIN && cp <= EMAGPIE_PATH_PERSISTENT) {
+    EMG_OK(relayout(c, cv, intensities_dev, s));
+    c->cfg.fft_plan = cv;
+    c->cfg.finalize_shape = cf;
+    c->cfg.path = cp;
+    EMG_HIP(emg::persistent_grid_size(m, cv, L, c->num_cus, &c->persist_grid));
+    EMG_HIP(hipStreamSynchronize(s));
+    fill_plan_info(c, 2);
+    return EMAGPIE_OK;
+  }
+  emagpie_plan& P = c->plan;
+  // scratch state (unit object, unit probe) and the epoch-0 scan order
+  float2* tobj = reinterpret_cast<float2*>(c->ws + c->lay.tune_obj.off);
+  float2* tprobe = reinterpret_cast<float2*>(c->ws + c->lay.tune_probe.off);
+  EMG_HIP(emg::launch_fill_c64(tobj, (size_t)c->cfg.n * c->cfg.n, make_float2(1.f, 0.f), s));
+  EMG_HIP(emg::launch_fill_c64(tprobe, (size_t)m * m, make_float2(1.f, 0.f), s));
+  std::vector<int32_t> perm(N);
+  fisher_yates(c->cfg.seed, 0, N, perm.data());
+  int4* pin = c->perm_pinned[0];
+  for (int j = 0; j < N; ++j) {
+    const int k = perm[j];
+    pin[j] = make_int4(k, c->pos_host[2 * k], c->pos_host[2 * k + 1], 0);
+  }
+  EMG_HIP(hipMemcpyAsync(c->slots, pin, sizeof(int4) * N, hipMemcpyHostToDevice, s));
+  EMG_HIP(hipStreamSynchronize(s));
+  const int b = std::min(B, N), nb = std::max(1, N / b);
+  auto batch_args = [&](int rep) {
+    emg::StepArgs a = base_args(c, tobj, tprobe);
+    a.slot = c->slots + (size_t)(rep % nb) * b;
+    a.b = b;
+    return a;
+  };
+  constexpr int kWarm = 2, kReps = 11;
+
+  // 1. FFT plan: time the patch-stage kernel of every candidate
+  if (req.fft_plan == EMAGPIE_TUNE) {
+    const int nv = emg::fft_plan_count(m);
+    P.n_fft_plans = nv;
+    int best = 0;
+    for (int v = 0; v < nv; ++v) {
+      EMG_OK(relayout(c, v, intensities_dev, s));
+      float ms = -1.f;
+      EMG_OK(time_kernel(s, kWarm, kReps, [&](int rep, hipEvent_t e0, hipEvent_t e1) -> emagpie_status {
+        EMG_HIP(emg::launch_patch_step(m, v, L, batch_args(rep), s, e0, e1));
+        return EMAGPIE_OK;
+      }, &ms));
+      P.fft_us[v] = 1000.f * ms;
+      if (P.fft_us[v] < P.fft_us[best]) best = v;
+    }
+    EMG_OK(relayout(c, best, intensities_dev, s));
+    c->cfg.fft_plan = best;
+    EMG_HIP(emg::persistent_grid_size(m, best, L, c->num_cus, &c->persist_grid));
+  }
+  // 2. finalize shape: time the finalize after an untimed patch stage
+  if (req.finalize_shape == EMAGPIE_TUNE) {
+    P.n_fin_shapes = emg::kFinShapes;
+    int best = 0;
+    for (int f = 0; f < emg::kFinShapes; ++f) {
+      float ms = -1.f;
+      EMG_OK(time_kernel(s, kWarm, kReps, [&](int rep, hipEvent_t e0, hipEvent_t e1) -> emagpie_status {
+        const emg::StepArgs a = batch_args(rep);
+        EMG_HIP(emg::launch_patch_step(m, c->cfg.fft_plan, L, a, s));
+        EMG_HIP(emg::launch_finalize(m, f, a, s, e0, e1));
+        return EMAGPIE_OK;
+      }, &ms));
+      P.fin_us[f] = 1000.f * ms;
+      if (P.fin_us[f] < P.fin_us[best]) best = f;
+    }
+    c->cfg.finalize_shape = best;
+  }
+  // 3. path: whole epochs on the scratch state
+  if (req.path == EMAGPIE_PATH_AUTO) {
+    const int cand[3] = {EMAGPIE_PATH_FUSED, EMAGPIE_PATH_GRAPH, EMAGPIE_PATH_PERSISTENT};
+    int best = EMAGPIE_PATH_FUSED;
+    for (int p : cand) {
+      c->cfg.path = p;
+      float ms = -1.f;
+      int64_t epoch = 0;
+      EMG_OK(time_kernel(s, 1, 3, [&](int, hipEvent_t e0, hipEvent_t e1) -> emagpie_status {
+        if (e0) EMG_HIP(hipEventRecord(e0, s));
+        EMG_OK(emagpie_epoch(c, tobj, tprobe, epoch++, nullptr, nullptr, s));
+        if (e1) EMG_HIP(hipEventRecord(e1, s));
+        return EMAGPIE_OK;
+      }, &ms));
+      P.path_ms[p] = ms;
+      if (P.path_ms[p] < P.path_ms[best]) best = p;
+    }
+    c->cfg.path = best;
+    drop_graph(c);
+  }
+  EMG_HIP(hipStreamSynchronize(s));
+  fill_plan_info(c, 1);
+  cache_append(req.tune_cache, key, P);
+  return EMAGPIE_OK;
 }
 
 }  // namespace
@@ -332,7 +587,14 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   if ((e = hipGetDevice(&dev)) != hipSuccess) return hipfail(e, "hipGetDevice");
   if ((e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return hipfail(e, "hipDeviceGetAttribute");
-  if ((e = emg::persistent_grid_size(c.m, c.levels, ctx->num_cus, &ctx->persist_grid)) != hipSuccess)
+  // the plan the context starts with: the configured one, or the defaults
+  // until the autotuner below has chosen
+  if (ctx->cfg.fft_plan == EMAGPIE_TUNE) ctx->cfg.fft_plan = 0;
+  if (ctx->cfg.finalize_shape == EMAGPIE_TUNE) ctx->cfg.finalize_shape = 0;
+  if (ctx->cfg.path == EMAGPIE_PATH_AUTO) ctx->cfg.path = EMAGPIE_PATH_FUSED;
+  ctx->layout_plan = ctx->cfg.fft_plan;
+  if ((e = emg::persistent_grid_size(c.m, ctx->cfg.fft_plan, c.levels, ctx->num_cus,
+                                     &ctx->persist_grid)) != hipSuccess)
     return hipfail(e, "occupancy query");
 
   // twiddles exp(-2 pi i j / m), evaluated in double on the host
@@ -353,7 +615,8 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   if ((e = hipMemcpyAsync(ctx->pos, p2.data(), c.n_pos * sizeof(int2), hipMemcpyHostToDevice, s)) != hipSuccess)
     return hipfail(e, "upload positions");
   if ((e = hipMemsetAsync(ctx->scal_i, 0, 64, s)) != hipSuccess) return hipfail(e, "clear flags");
-  if ((e = emg::launch_layout_intensities(c.m, intensities_dev, ctx->dperm, c.n_pos, ctx->phi_all,
+  if ((e = emg::launch_layout_intensities(c.m, ctx->layout_plan, intensities_dev, ctx->dperm, c.n_pos,
+                                           ctx->phi_all,
                                            ctx->scal_i, s)) != hipSuccess)
     return hipfail(e, "layout intensities");
   if ((e = emg::launch_sum_doubles(ctx->phi_all, c.n_pos, ctx->scal_d, s)) != hipSuccess)
@@ -378,8 +641,37 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
     if ((e = hipEventCreateWithFlags(&ctx->perm_ev[i], hipEventDisableTiming)) != hipSuccess)
       return hipfail(e, "event");
   }
+  fill_plan_info(ctx, 0);
+  if (wants_tuning(c)) {
+    emagpie_status ts = autotune(ctx, c, intensities_dev, s);
+    if (ts != EMAGPIE_OK) return bail(ts);
+  }
+  ctx->cfg.tune_cache = nullptr;  // the caller's string is only read during init
   *out = ctx;
   g_err.clear();
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_plan_get(emagpie_ctx ctx, emagpie_plan* out_host) {
+  if (!ctx || !out_host) return fail(EMAGPIE_E_ARG, "null argument");
+  *out_host = ctx->plan;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_plan_describe(int32_t m, int32_t fft_plan, int32_t finalize_shape,
+                                     emagpie_plan* out_host, int32_t* count_host) {
+  if (count_host) *count_host = emg::fft_plan_count(m);
+  if (!out_host) return fail(EMAGPIE_E_ARG, "null output");
+  emagpie_plan p{};
+  if (!emg::fft_plan_desc(m, fft_plan, &p.r1, &p.r2, &p.threads))
+    return fail(EMAGPIE_E_ARG, "no such FFT plan for this m");
+  if (!emg::fin_shape_desc(finalize_shape, &p.fin_threads, &p.fin_tile))
+    return fail(EMAGPIE_E_ARG, "no such finalize shape");
+  p.fft_plan = fft_plan;
+  p.finalize_shape = finalize_shape;
+  p.path = -1;
+  for (float& x : p.path_ms) x = -1.f;
+  *out_host = p;
   return EMAGPIE_OK;
 }
 
@@ -527,7 +819,8 @@ emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, in
       hipEvent_t e0, e1;
       EMG_OK(take_pair(ctx, 2, true, &e0, &e1));
       if (e0) EMG_HIP(hipEventRecord(e0, s));
-      EMG_HIP(emg::launch_persistent_epoch(ctx->cfg.m, ctx->cfg.levels, a, N, ctx->cfg.minibatch,
+      EMG_HIP(emg::launch_persistent_epoch(ctx->cfg.m, ctx->cfg.fft_plan, ctx->cfg.levels, a, N,
+                                           ctx->cfg.minibatch,
                                            ctx->persist_grid, ctx->bar, ctx->bar_base,
                                            ctx->scal_i + 2, &used, s));
       if (e1) EMG_HIP(hipEventRecord(e1, s));
@@ -553,7 +846,7 @@ emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void
   a.b = b;
   a.phi = nullptr;
   a.zplus = static_cast<float2*>(zplus_dev);
-  EMG_HIP(emg::launch_patch_step(ctx->cfg.m, ctx->cfg.levels, a, s));
+  EMG_HIP(emg::launch_patch_step(ctx->cfg.m, ctx->cfg.fft_plan, ctx->cfg.levels, a, s));
   return EMAGPIE_OK;
 }
 
@@ -561,7 +854,8 @@ emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* 
                               double* misfit_dev, void* stream) {
   if (!ctx || !obj_dev || !probe_dev || !misfit_dev) return fail(EMAGPIE_E_ARG, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  EMG_HIP(emg::launch_misfit_terms(ctx->cfg.m, static_cast<const float2*>(obj_dev), ctx->cfg.n,
+  EMG_HIP(emg::launch_misfit_terms(ctx->cfg.m, ctx->cfg.fft_plan, static_cast<const float2*>(obj_dev),
+                                   ctx->cfg.n,
                                    static_cast<const float2*>(probe_dev), ctx->dperm, ctx->pos,
                                    ctx->cfg.n_pos, ctx->tw32, ctx->phi_all, s));
   EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
@@ -591,7 +885,7 @@ emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* pr
   g.gz_slots = ctx->ws + ctx->lay.gz.off;
   g.gq_slots = ctx->ws + ctx->lay.gq.off;
   g.phi_all = ctx->phi_all;
-  EMG_HIP(emg::launch_grad(ctx->cfg.m, f64, g, s));
+  EMG_HIP(emg::launch_grad(ctx->cfg.m, ctx->cfg.fft_plan, f64, g, s));
   if (misfit_dev) EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
   return EMAGPIE_OK;
 }
@@ -604,7 +898,7 @@ emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* pr
 namespace {
 
 struct GroupClass {
-  int m, L;
+  int m, L, v, f;  // probe side, levels, FFT plan, finalize shape
   std::vector<int> inst;
   std::vector<size_t> patch_off, fin_off;  // per step: offset into the work arrays
   std::vector<int> patch_n, fin_n;         // per step: blocks
@@ -637,9 +931,9 @@ emagpie_status plan_group(int32_t n_inst, const emagpie_ctx* ctxs, GroupLayout* 
     const emagpie_config& c = ctxs[i]->cfg;
     GroupClass* cls = nullptr;
     for (auto& k : G->classes)
-      if (k.m == c.m && k.L == c.levels) cls = &k;
+      if (k.m == c.m && k.L == c.levels && k.v == c.fft_plan && k.f == c.finalize_shape) cls = &k;
     if (!cls) {
-      G->classes.push_back(GroupClass{c.m, c.levels, {}, {}, {}, {}, {}});
+      G->classes.push_back(GroupClass{c.m, c.levels, c.fft_plan, c.finalize_shape, {}, {}, {}, {}, {}});
       cls = &G->classes.back();
     }
     cls->inst.push_back(i);
@@ -659,7 +953,7 @@ emagpie_status plan_group(int32_t n_inst, const emagpie_ctx* ctxs, GroupLayout* 
         const emagpie_config& c = ctxs[i]->cfg;
         if (j * c.minibatch >= c.n_pos) continue;
         int items = 0;
-        if (emg::finalize_item_count(c.m, c.n, &items) != hipSuccess)
+        if (emg::finalize_item_count(c.m, c.finalize_shape, c.n, &items) != hipSuccess)
           return fail(EMAGPIE_E_SHAPE, "unsupported probe size in group");
         for (int t = 0; t < items; ++t) G->work_host.push_back(make_int2(j * n_inst + i, t));
       }
@@ -846,10 +1140,11 @@ emagpie_status emagpie_group_epoch(emagpie_group g, void* const* obj_devs, void*
       ce = hipStreamWaitEvent(sc, g->fork_join[0], 0);
       for (int j = 0; ce == hipSuccess && j < J; ++j) {
         if (k.patch_n[j] > 0)
-          ce = emg::launch_patch_step_multi(k.m, k.L, g->args_dev, g->work_dev + k.patch_off[j],
+          ce = emg::launch_patch_step_multi(k.m, k.v, k.L, g->args_dev, g->work_dev + k.patch_off[j],
                                             k.patch_n[j], sc);
         if (ce == hipSuccess && k.fin_n[j] > 0)
-          ce = emg::launch_finalize_multi(k.m, g->args_dev, g->work_dev + k.fin_off[j], k.fin_n[j], sc);
+          ce = emg::launch_finalize_multi(k.m, k.f, g->args_dev, g->work_dev + k.fin_off[j], k.fin_n[j],
+                                          sc);
       }
       if (ce == hipSuccess) ce = hipEventRecord(g->fork_join[1 + c], sc);
       if (ce == hipSuccess) ce = hipStreamWaitEvent(s0, g->fork_join[1 + c], 0);

@@ -12,6 +12,7 @@
 // Per-pixel work between the two transforms (the modulus projection) reads
 // its amplitudes in the same transform order, laid out once at init.
 //
+// The factorisation and the threads per tile are a plan (plans.hpp).
 // LDS rows are padded by one element (row stride m + 1) so that the
 // line-parallel thread mapping used for both row and column passes is free
 // of bank conflicts.  Twiddles W_m^j = exp(-2 pi i j / m), j < m, come from a
@@ -20,6 +21,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "plans.hpp"
 
 namespace emg {
 
@@ -61,20 +64,13 @@ __device__ __forceinline__ cx<T> rot90(cx<T> a) {
   return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
 }
 
-// Factorisation and workgroup size per probe side (m^2 / 4 threads, at most
-// 1024: each thread owns 2 x 2 pixel blocks in the per-pixel phases).
-template <int M> struct Plan;
-template <> struct Plan<32> { static constexpr int R1 = 8, R2 = 4, NT = 256; };
-template <> struct Plan<64> { static constexpr int R1 = 8, R2 = 8, NT = 1024; };
-template <> struct Plan<128> { static constexpr int R1 = 16, R2 = 8, NT = 1024; };
-
 template <int M>
 __host__ __device__ constexpr int lds_stride() { return M + 1; }
 
-// frequency held at LDS position p after a forward pass pair
-template <int M>
+// frequency held at LDS position p after a forward pass pair of plan (M, V)
+template <int M, int V>
 __host__ __device__ __forceinline__ int freq_of_pos(int p) {
-  return p / Plan<M>::R1 + Plan<M>::R2 * (p % Plan<M>::R1);
+  return p / Plan<M, V>::R1 + Plan<M, V>::R2 * (p % Plan<M, V>::R1);
 }
 
 // ---------------------------------------------------------------------------
@@ -164,9 +160,9 @@ __device__ __forceinline__ void dft_small(cx<T>* v, const cx<T>* tw) {
 //   inverse strided pass multiplies input j by conj(W^(g j)) before it.
 // Work item w -> line = w % M (line fastest: conflict-free with stride M+1).
 // ---------------------------------------------------------------------------
-template <typename T, int M, bool INV, bool STRIDED, bool COLS>
+template <typename T, int M, int V, bool INV, bool STRIDED, bool COLS>
 __device__ __forceinline__ void fft_pass(cx<T>* A, const cx<T>* tw, int tid) {
-  constexpr int R1 = Plan<M>::R1, R2 = Plan<M>::R2, NT = Plan<M>::NT;
+  constexpr int R1 = Plan<M, V>::R1, R2 = Plan<M, V>::R2, NT = Plan<M, V>::NT;
   constexpr int R = STRIDED ? R2 : R1;
   constexpr int G = STRIDED ? R1 : R2;
   constexpr int ITEMS = M * G;
@@ -206,28 +202,28 @@ __device__ __forceinline__ void fft_pass(cx<T>* A, const cx<T>* tw, int tid) {
 
 // Forward 2-D DFT: natural order in, transform order out.  Caller must have
 // synchronised after filling A; returns after a final barrier.
-template <typename T, int M>
+template <typename T, int M, int V>
 __device__ __forceinline__ void fft2_forward(cx<T>* A, const cx<T>* tw, int tid) {
-  fft_pass<T, M, false, true, false>(A, tw, tid);
+  fft_pass<T, M, V, false, true, false>(A, tw, tid);
   __syncthreads();
-  fft_pass<T, M, false, false, false>(A, tw, tid);
+  fft_pass<T, M, V, false, false, false>(A, tw, tid);
   __syncthreads();
-  fft_pass<T, M, false, true, true>(A, tw, tid);
+  fft_pass<T, M, V, false, true, true>(A, tw, tid);
   __syncthreads();
-  fft_pass<T, M, false, false, true>(A, tw, tid);
+  fft_pass<T, M, V, false, false, true>(A, tw, tid);
   __syncthreads();
 }
 
 // Inverse 2-D DFT without the 1/m^2 factor: transform order in, natural out.
-template <typename T, int M>
+template <typename T, int M, int V>
 __device__ __forceinline__ void fft2_inverse(cx<T>* A, const cx<T>* tw, int tid) {
-  fft_pass<T, M, true, false, true>(A, tw, tid);
+  fft_pass<T, M, V, true, false, true>(A, tw, tid);
   __syncthreads();
-  fft_pass<T, M, true, true, true>(A, tw, tid);
+  fft_pass<T, M, V, true, true, true>(A, tw, tid);
   __syncthreads();
-  fft_pass<T, M, true, false, false>(A, tw, tid);
+  fft_pass<T, M, V, true, false, false>(A, tw, tid);
   __syncthreads();
-  fft_pass<T, M, true, true, false>(A, tw, tid);
+  fft_pass<T, M, V, true, true, false>(A, tw, tid);
   __syncthreads();
 }
 

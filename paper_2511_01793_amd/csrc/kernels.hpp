@@ -1,4 +1,7 @@
-// gfx950 kernels of the eMAGPIE epoch and their launchers.
+// gfx950 kernels of the eMAGPIE epoch and their launchers, templated on the
+// probe side M, the FFT plan variant V, the multigrid depth L and the finalize
+// shape F (plans.hpp).  Each probe side is instantiated in a translation unit
+// of its own (kernels_m32.hip, kernels_m64.hip, kernels_m128.hip).
 //
 // One workgroup owns one m x m scan patch in the patch stage: it gathers the
 // object window, forms the exit wave psi = Q . z_k (Def. 2.1), runs the
@@ -17,8 +20,12 @@
 // previous one wrote), so at the benchmark's sizes the patch stage is bound by
 // latency, not bandwidth: a patch gets up to 1024 threads (16 waves) and each
 // thread loads its probe, object and amplitude values once, up front.
+#pragma once
+
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "device_fft.hpp"
 #include "launch.hpp"
@@ -137,44 +144,49 @@ __device__ __forceinline__ void st_pair(float2* p, size_t i, cx<float> a, cx<flo
   *reinterpret_cast<float4*>(p + i) = make_float4(a.re, a.im, b.re, b.im);
 }
 
-template <int M>
+template <int M, int V>
 struct Px {
-  static constexpr int NT = Plan<M>::NT, LS = lds_stride<M>();
+  static constexpr int NT = Plan<M, V>::NT, LS = lds_stride<M>();
   // every thread owns 2 x 2 pixel blocks: one per round, ROUNDS rounds
-  // (quadrants of 64 x 64 when the tile has more pixels than 4 x NT)
   static constexpr int ROUNDS = M * M / (4 * NT);
   static constexpr int PX = 4 * ROUNDS;  // pixels per thread
-  static constexpr int QW = (ROUNDS == 1 ? M : 64) / 4;  // 4 x 4 regions per row of a round
+  // a round covers RH x RW pixels (RW = min(M, 64) columns); RPC rounds sit
+  // side by side, and the round rows stack downwards
+  static constexpr int RW = M < 64 ? M : 64;
+  static constexpr int RH = 4 * NT / RW;
+  static constexpr int RPC = M / RW;
+  static constexpr int QW = RW / 4;  // 4 x 4 regions per row of a round
   // one round: keep the thread's probe / object values in registers from the
   // gather to the numerators; several rounds reload them (register budget)
   static constexpr bool CACHE = ROUNDS == 1;
+  static_assert(ROUNDS * 4 * NT == M * M && RH % 4 == 0 && RH * (ROUNDS / RPC) == M, "round tiling");
 };
 
 // Top-left pixel (r0, c0) of the thread's 2 x 2 block in round rd (c0 is even).
-template <int M>
+template <int M, int V>
 __device__ __forceinline__ void blk_origin(int tid, int rd, int& r0, int& c0) {
-  constexpr int QW = Px<M>::QW;
+  using P = Px<M, V>;
   const int q = tid >> 2, sub = tid & 3;
-  r0 = 4 * (q / QW) + 2 * (sub >> 1);
-  c0 = 4 * (q % QW) + 2 * (sub & 1);
-  if constexpr (Px<M>::ROUNDS > 1) {
-    r0 += 64 * (rd >> 1);
-    c0 += 64 * (rd & 1);
+  r0 = 4 * (q / P::QW) + 2 * (sub >> 1);
+  c0 = 4 * (q % P::QW) + 2 * (sub & 1);
+  if constexpr (P::ROUNDS > 1) {
+    r0 += P::RH * (rd / P::RPC);
+    c0 += P::RW * (rd % P::RPC);
   }
 }
 
 // Pixel e of a thread: round e / 4, position (e / 2 % 2, e % 2) inside that
 // round's 2 x 2 block.  Four consecutive lanes own the four 2 x 2 blocks of one
 // 4 x 4 region, so a region-wide sum is two quad lane exchanges.
-template <int M>
+template <int M, int V>
 __device__ __forceinline__ void pix_rc(int tid, int e, int& r, int& c) {
-  constexpr int QW = Px<M>::QW;
+  using P = Px<M, V>;
   const int q = tid >> 2, sub = tid & 3, round = e >> 2;
-  r = 4 * (q / QW) + 2 * (sub >> 1) + ((e >> 1) & 1);
-  c = 4 * (q % QW) + 2 * (sub & 1) + (e & 1);
-  if constexpr (Px<M>::ROUNDS > 1) {
-    r += 64 * (round >> 1);
-    c += 64 * (round & 1);
+  r = 4 * (q / P::QW) + 2 * (sub >> 1) + ((e >> 1) & 1);
+  c = 4 * (q % P::QW) + 2 * (sub & 1) + (e & 1);
+  if constexpr (P::ROUNDS > 1) {
+    r += P::RH * (round / P::RPC);
+    c += P::RW * (round % P::RPC);
   }
 }
 
@@ -183,15 +195,15 @@ __device__ __forceinline__ void pix_rc(int tid, int e, int& r, int& c) {
 //   load(rd, r0, c0, q, z, R) fills the probe, object window and revised exit
 //   wave of the block at (r0, c0); element 2 i + j is pixel (r0 + i, c0 + j)
 // ---------------------------------------------------------------------------
-template <int M, int L, class LOAD>
+template <int M, int V, int L, class LOAD>
 __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, LOAD load,
                                              float qqmax, float zmax) {
   const size_t base = (size_t)s * M * M;
   const bool slot_den = a.pden_slot != nullptr;
 #pragma unroll
-  for (int rd = 0; rd < Px<M>::ROUNDS; ++rd) {
+  for (int rd = 0; rd < Px<M, V>::ROUNDS; ++rd) {
     int r0, c0;
-    blk_origin<M>(tid, rd, r0, c0);
+    blk_origin<M, V>(tid, rd, r0, c0);
     cx<float> q[4], zz[4], R[4];
     load(rd, r0, c0, q, zz, R);
     float q2[4], u[4];
@@ -284,11 +296,12 @@ __device__ __forceinline__ float project_px(cx<float>& P, float dval) {
 // ---------------------------------------------------------------------------
 // the whole patch stage for slot s, LDS-resident
 // ---------------------------------------------------------------------------
-template <int M, int L>
+template <int M, int V, int L>
 __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* A,
                                            const cx<float>* tws, float* redf, double* redd,
                                            int tid) {
-  constexpr int R = Px<M>::ROUNDS, NT = Px<M>::NT, LS = Px<M>::LS;
+  using P = Px<M, V>;
+  constexpr int R = P::ROUNDS, NT = P::NT, LS = P::LS;
   const int4 sl = a.slot[s];
   const int k = sl.x;
   const size_t n = (size_t)a.n;
@@ -297,13 +310,13 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
   // every global load of the patch is issued here, before any dependent work:
   // probe rows as 16-byte pairs, amplitude rows as 8-byte pairs, the object
   // window (arbitrary alignment) per pixel
-  cx<float> qc[Px<M>::CACHE ? 4 : 1], zc[Px<M>::CACHE ? 4 : 1];
+  cx<float> qc[P::CACHE ? 4 : 1], zc[P::CACHE ? 4 : 1];
   float amp[4 * R];
   float q2m = 0.f, z2m = 0.f;
 #pragma unroll
   for (int rd = 0; rd < R; ++rd) {
     int r0, c0;
-    blk_origin<M>(tid, rd, r0, c0);
+    blk_origin<M, V>(tid, rd, r0, c0);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const float2 dv = *reinterpret_cast<const float2*>(dk + (r0 + i) * M + c0);
@@ -316,7 +329,7 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
 #pragma unroll
   for (int rd = 0; rd < R; ++rd) {
     int r0, c0;
-    blk_origin<M>(tid, rd, r0, c0);
+    blk_origin<M, V>(tid, rd, r0, c0);
     cx<float> q[4], zz[4];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -326,7 +339,7 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      if constexpr (Px<M>::CACHE) {
+      if constexpr (P::CACHE) {
         qc[e] = q[e];
         zc[e] = zz[e];
       }
@@ -339,12 +352,12 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
   // before they are read in the per-pixel phase
   wave_max2_to_lds<NT>(q2m, z2m, redf, tid);
   __syncthreads();
-  fft2_forward<float, M>(A, tws, tid);
+  fft2_forward<float, M, V>(A, tws, tid);
   double acc = 0.0;
 #pragma unroll
   for (int rd = 0; rd < R; ++rd) {
     int r0, c0;
-    blk_origin<M>(tid, rd, r0, c0);
+    blk_origin<M, V>(tid, rd, r0, c0);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       acc += (double)project_amp<M>(A[(r0 + (e >> 1)) * LS + c0 + (e & 1)], amp[4 * rd + e]);
@@ -352,15 +365,15 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
   acc = wave_sum(acc);
   if ((tid & 63) == 0) redd[tid >> 6] = acc;
   __syncthreads();
-  fft2_inverse<float, M>(A, tws, tid);
+  fft2_inverse<float, M, V>(A, tws, tid);
   float qqmax, zmax;
   lds_max2<NT>(redf, qqmax, zmax);
-  pixel_update<M, L>(
+  pixel_update<M, V, L>(
       a, s, tid,
       [&](int rd, int r0, int c0, cx<float>* q, cx<float>* zz, cx<float>* Rv) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          if constexpr (Px<M>::CACHE) {
+          if constexpr (P::CACHE) {
             q[2 * i] = qc[2 * i];
             q[2 * i + 1] = qc[2 * i + 1];
             zz[2 * i] = zc[2 * i];
@@ -386,11 +399,17 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
 //   probe units: 64 pixels x 4 slot groups per 256 threads, groups combined in
 //   a fixed order, then the joint step.
 // ---------------------------------------------------------------------------
-template <int FNT>
+template <int FNT, int T_>
 struct Fin {
-  static constexpr int T = FNT == 256 ? 32 : (FNT == 1024 ? 64 : 16);
+  static constexpr int T = T_;
   static constexpr int PER = T * T / FNT;
   static constexpr int PROBE_PX = FNT / 4;  // probe pixels per item
+  static_assert(PER * FNT == T * T && FNT % 256 == 0, "finalize shape");
+};
+// the finalize shape used inside the persistent kernel (FNT = the plan's NT)
+template <int NT>
+struct PersistFin {
+  static constexpr int T = NT >= 1024 ? 64 : 32;
 };
 
 struct FinLds {
@@ -401,12 +420,11 @@ struct FinLds {
   float pe[1024];
 };
 
-template <int M, int FNT>
+template <int M, int FNT, int T>
 __host__ __device__ inline int finalize_items(int n, int* ntiles_out) {
-  constexpr int T = Fin<FNT>::T;
   const int tpr = (n + T - 1) / T;
   *ntiles_out = tpr * tpr;
-  return tpr * tpr + (M * M + Fin<FNT>::PROBE_PX - 1) / Fin<FNT>::PROBE_PX;
+  return tpr * tpr + (M * M + Fin<FNT, T>::PROBE_PX - 1) / Fin<FNT, T>::PROBE_PX;
 }
 
 template <int M, int FNT>
@@ -414,10 +432,10 @@ __device__ __forceinline__ void load_slot_positions(const StepArgs& a, FinLds& L
   for (int s = tid; s < a.b; s += FNT) L.spos[s] = make_int2(a.slot[s].y, a.slot[s].z);
 }
 
-template <int M, int FNT>
+template <int M, int FNT, int T>
 __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int ntiles, FinLds& L,
                                               int tid) {
-  constexpr int T = Fin<FNT>::T, PER = Fin<FNT>::PER;
+  constexpr int PER = Fin<FNT, T>::PER;
   const int n = a.n;
   if (item < ntiles) {
     const int tpr = (n + T - 1) / T;
@@ -494,7 +512,7 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
   } else {
     const int lt = tid & 255, unit = tid >> 8;
     const int g = lt >> 6;
-    const int r = (item - ntiles) * Fin<FNT>::PROBE_PX + unit * 64 + (lt & 63);
+    const int r = (item - ntiles) * Fin<FNT, T>::PROBE_PX + unit * 64 + (lt & 63);
     const bool live = a.update_probe && r < M * M;
     const int per = (a.b + 3) / 4;
     const int s_lo = g * per, s_hi = min(a.b, s_lo + per);
@@ -550,24 +568,22 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
 // ---------------------------------------------------------------------------
 // fused path kernels
 // ---------------------------------------------------------------------------
-template <int M>
+template <int M, int NT>
 __device__ __forceinline__ void stage_twiddles(const float2* tw, cx<float>* tws, int tid) {
-  for (int j = tid; j < M; j += Plan<M>::NT) tws[j] = ld(tw, j);
+  for (int j = tid; j < M; j += NT) tws[j] = ld(tw, j);
 }
 
-template <int M, int L>
-__global__ __launch_bounds__(Plan<M>::NT) void k_patch_step(StepArgs a) {
+template <int M, int V, int L>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step(StepArgs a) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ float redf[32];
   __shared__ double redd[16];
   const int tid = threadIdx.x;
-  stage_twiddles<M>(a.tw, tws, tid);
+  stage_twiddles<M, Plan<M, V>::NT>(a.tw, tws, tid);
   __syncthreads();
-  patch_step<M, L>(a, blockIdx.x, A, tws, redf, redd, tid);
+  patch_step<M, V, L>(a, blockIdx.x, A, tws, redf, redd, tid);
 }
-
-constexpr int kFinNT = 256;
 
 // ---------------------------------------------------------------------------
 // many independent reconstructions in one launch: block b serves work item
@@ -575,9 +591,9 @@ constexpr int kFinNT = 256;
 // instance keeps its own state, data and workspace, so the arithmetic is the
 // single-instance arithmetic
 // ---------------------------------------------------------------------------
-template <int M, int L>
-__global__ __launch_bounds__(Plan<M>::NT) void k_patch_step_multi(const StepArgs* args,
-                                                                  const int2* work) {
+template <int M, int V, int L>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step_multi(const StepArgs* args,
+                                                                     const int2* work) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ float redf[32];
@@ -585,31 +601,34 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_patch_step_multi(const StepArgs
   const int tid = threadIdx.x;
   const int2 w = work[blockIdx.x];
   const StepArgs a = args[w.x];
-  stage_twiddles<M>(a.tw, tws, tid);
+  stage_twiddles<M, Plan<M, V>::NT>(a.tw, tws, tid);
   __syncthreads();
-  patch_step<M, L>(a, w.y, A, tws, redf, redd, tid);
+  patch_step<M, V, L>(a, w.y, A, tws, redf, redd, tid);
 }
 
-template <int M>
-__global__ __launch_bounds__(kFinNT) void k_finalize(StepArgs a, int ntiles) {
+template <int M, int F>
+__global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize(StepArgs a, int ntiles) {
+  constexpr int FNT = FinShape<F>::FNT, T = FinShape<F>::T;
   __shared__ FinLds L;
   const int tid = threadIdx.x;
-  load_slot_positions<M, kFinNT>(a, L, tid);
+  load_slot_positions<M, FNT>(a, L, tid);
   __syncthreads();
-  finalize_item<M, kFinNT>(a, blockIdx.x, ntiles, L, tid);
+  finalize_item<M, FNT, T>(a, blockIdx.x, ntiles, L, tid);
 }
 
-template <int M>
-__global__ __launch_bounds__(kFinNT) void k_finalize_multi(const StepArgs* args, const int2* work) {
+template <int M, int F>
+__global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize_multi(const StepArgs* args,
+                                                                    const int2* work) {
+  constexpr int FNT = FinShape<F>::FNT, T = FinShape<F>::T;
   __shared__ FinLds L;
   const int tid = threadIdx.x;
   const int2 w = work[blockIdx.x];
   const StepArgs a = args[w.x];
   int ntiles;
-  finalize_items<M, kFinNT>(a.n, &ntiles);
-  load_slot_positions<M, kFinNT>(a, L, tid);
+  finalize_items<M, FNT, T>(a.n, &ntiles);
+  load_slot_positions<M, FNT>(a, L, tid);
   __syncthreads();
-  finalize_item<M, kFinNT>(a, w.y, ntiles, L, tid);
+  finalize_item<M, FNT, T>(a, w.y, ntiles, L, tid);
 }
 
 // Grid-wide barrier for the persistent kernel (all workgroups co-resident by
@@ -639,19 +658,19 @@ __device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned target, int
 }
 
 // persistent epoch: every minibatch of a sweep in one cooperative launch
-template <int M, int L>
-__global__ __launch_bounds__(Plan<M>::NT) void k_epoch_persistent(StepArgs a, int n_pos, int B,
-                                                                  int ntiles, int nitems,
-                                                                  unsigned* bar, unsigned bar_base,
-                                                                  int* err) {
+template <int M, int V, int L>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_epoch_persistent(StepArgs a, int n_pos, int B,
+                                                                     int ntiles, int nitems,
+                                                                     unsigned* bar,
+                                                                     unsigned bar_base, int* err) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ float redf[32];
   __shared__ double redd[16];
   __shared__ FinLds FL;
-  constexpr int NT = Plan<M>::NT;
+  constexpr int NT = Plan<M, V>::NT, FT = PersistFin<NT>::T;
   const int tid = threadIdx.x;
-  stage_twiddles<M>(a.tw, tws, tid);
+  stage_twiddles<M, NT>(a.tw, tws, tid);
   __syncthreads();
   const int4* slots = a.slot;
   unsigned target = bar_base;
@@ -659,13 +678,14 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_epoch_persistent(StepArgs a, in
     StepArgs x = a;
     x.slot = slots + start;
     x.b = min(B, n_pos - start);
-    for (int s = blockIdx.x; s < x.b; s += gridDim.x) patch_step<M, L>(x, s, A, tws, redf, redd, tid);
+    for (int s = blockIdx.x; s < x.b; s += gridDim.x)
+      patch_step<M, V, L>(x, s, A, tws, redf, redd, tid);
     target += gridDim.x;
     grid_barrier(bar, target, err);
     load_slot_positions<M, NT>(x, FL, tid);
     __syncthreads();
     for (int item = blockIdx.x; item < nitems; item += gridDim.x)
-      finalize_item<M, NT>(x, item, ntiles, FL, tid);
+      finalize_item<M, NT, FT>(x, item, ntiles, FL, tid);
     target += gridDim.x;
     grid_barrier(bar, target, err);
   }
@@ -674,55 +694,55 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_epoch_persistent(StepArgs a, in
 // ---------------------------------------------------------------------------
 // plain path: one launch per stage, intermediates in HBM
 // ---------------------------------------------------------------------------
-template <int M>
-__global__ __launch_bounds__(Plan<M>::NT) void k_probe_prep(StepArgs a) {
+template <int M, int V>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_probe_prep(StepArgs a) {
   __shared__ float redf[32];
   const int tid = threadIdx.x;
   float q2m = 0.f, dummy = 0.f;
-  for (int r = tid; r < M * M; r += Plan<M>::NT) q2m = fmaxf(q2m, norm2(ld(a.probe, r)));
-  block_max2<Plan<M>::NT>(q2m, dummy, redf, tid);
+  for (int r = tid; r < M * M; r += Plan<M, V>::NT) q2m = fmaxf(q2m, norm2(ld(a.probe, r)));
+  block_max2<Plan<M, V>::NT>(q2m, dummy, redf, tid);
   if (tid == 0) a.qqmax[0] = q2m;
 }
 
-template <int M>
-__global__ __launch_bounds__(Plan<M>::NT) void k_gather(StepArgs a) {
+template <int M, int V>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_gather(StepArgs a) {
   __shared__ float redf[32];
-  constexpr int PX = Px<M>::PX;
+  constexpr int PX = Px<M, V>::PX;
   const int tid = threadIdx.x, s = blockIdx.x;
   const float2* zwin = a.obj + (size_t)a.slot[s].y * a.n + a.slot[s].z;
   float z2m = 0.f, dummy = 0.f;
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
     int r, c;
-    pix_rc<M>(tid, e, r, c);
+    pix_rc<M, V>(tid, e, r, c);
     const cx<float> q = ld(a.probe, (size_t)r * M + c);
     const cx<float> zz = ld(zwin, (size_t)r * a.n + c);
     z2m = fmaxf(z2m, norm2(zz));
     st(a.stack, (size_t)s * M * M + r * M + c, mul(q, zz));
   }
-  block_max2<Plan<M>::NT>(z2m, dummy, redf, tid);
+  block_max2<Plan<M, V>::NT>(z2m, dummy, redf, tid);
   if (tid == 0) a.zmax[s] = z2m;
 }
 
-template <int M, bool INV>
-__global__ __launch_bounds__(Plan<M>::NT) void k_fft(StepArgs a) {
+template <int M, int V, bool INV>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_fft(StepArgs a) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
-  constexpr int NT = Plan<M>::NT, LS = lds_stride<M>();
+  constexpr int NT = Plan<M, V>::NT, LS = lds_stride<M>();
   const int tid = threadIdx.x;
   float2* X = a.stack + (size_t)blockIdx.x * M * M;
-  stage_twiddles<M>(a.tw, tws, tid);
+  stage_twiddles<M, NT>(a.tw, tws, tid);
   for (int e = tid; e < M * M; e += NT) A[(e / M) * LS + e % M] = ld(X, e);
   __syncthreads();
-  if (INV) fft2_inverse<float, M>(A, tws, tid);
-  else fft2_forward<float, M>(A, tws, tid);
+  if (INV) fft2_inverse<float, M, V>(A, tws, tid);
+  else fft2_forward<float, M, V>(A, tws, tid);
   for (int e = tid; e < M * M; e += NT) st(X, e, A[(e / M) * LS + e % M]);
 }
 
-template <int M>
-__global__ __launch_bounds__(Plan<M>::NT) void k_project(StepArgs a) {
+template <int M, int V>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_project(StepArgs a) {
   __shared__ double redd[16];
-  constexpr int PX = Px<M>::PX, NT = Px<M>::NT;
+  constexpr int PX = Px<M, V>::PX, NT = Px<M, V>::NT;
   const int tid = threadIdx.x, s = blockIdx.x;
   float2* X = a.stack + (size_t)s * M * M;
   const float* dk = a.dperm + (size_t)a.slot[s].x * M * M;
@@ -730,7 +750,7 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_project(StepArgs a) {
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
     int r, c;
-    pix_rc<M>(tid, e, r, c);
+    pix_rc<M, V>(tid, e, r, c);
     const size_t o = (size_t)r * M + c;
     cx<float> P = ld(X, o);
     acc += (double)project_px<M>(P, dk[o]);
@@ -740,13 +760,13 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_project(StepArgs a) {
   if (tid == 0 && a.phi) a.phi[s] = tot / (2.0 * M * M);
 }
 
-template <int M, int L>
-__global__ __launch_bounds__(Plan<M>::NT) void k_numerators(StepArgs a) {
+template <int M, int V, int L>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_numerators(StepArgs a) {
   const int tid = threadIdx.x, s = blockIdx.x;
   const size_t n = (size_t)a.n;
   const float2* zwin = a.obj + (size_t)a.slot[s].y * n + a.slot[s].z;
   const float2* Rg = a.stack + (size_t)s * M * M;
-  pixel_update<M, L>(
+  pixel_update<M, V, L>(
       a, s, tid,
       [&](int rd, int r0, int c0, cx<float>* q, cx<float>* zz, cx<float>* Rv) {
 #pragma unroll
@@ -763,34 +783,34 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_numerators(StepArgs a) {
 // ---------------------------------------------------------------------------
 // misfit and gradient
 // ---------------------------------------------------------------------------
-template <int M>
-__global__ __launch_bounds__(Plan<M>::NT) void k_misfit(const float2* obj, int n,
+template <int M, int V>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, int n,
                                                         const float2* probe, const float* dperm,
                                                         const int2* pos, const float2* tw,
                                                         double* phi_all) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ double redd[16];
-  constexpr int PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
+  constexpr int PX = Px<M, V>::PX, NT = Px<M, V>::NT, LS = Px<M, V>::LS;
   const int tid = threadIdx.x, k = blockIdx.x;
   const int2 pk = pos[k];
   const float* dk = dperm + (size_t)k * M * M;
-  stage_twiddles<M>(tw, tws, tid);
+  stage_twiddles<M, NT>(tw, tws, tid);
   float dv[PX];
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
     int r, c;
-    pix_rc<M>(tid, e, r, c);
+    pix_rc<M, V>(tid, e, r, c);
     dv[e] = dk[r * M + c];
     A[r * LS + c] = mul(ld(probe, (size_t)r * M + c), ld(obj, (size_t)(pk.x + r) * n + pk.y + c));
   }
   __syncthreads();
-  fft2_forward<float, M>(A, tws, tid);
+  fft2_forward<float, M, V>(A, tws, tid);
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
     int r, c;
-    pix_rc<M>(tid, e, r, c);
+    pix_rc<M, V>(tid, e, r, c);
     acc += (double)project_px<M>(A[r * LS + c], dv[e]);
   }
   const double tot = block_sum<NT>(acc, redd, tid);
@@ -806,12 +826,12 @@ __device__ __forceinline__ void stT(void* p, size_t i, cx<T> v) {
   reinterpret_cast<cx<T>*>(p)[i] = v;
 }
 
-template <typename T, int M>
-__global__ __launch_bounds__(Plan<M>::NT) void k_grad_patch(GradArgs g, int k0) {
+template <typename T, int M, int V>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_grad_patch(GradArgs g, int k0) {
   __shared__ cx<T> A[M * lds_stride<M>()];
   __shared__ cx<T> tws[M];
   __shared__ double redd[16];
-  constexpr int PX = Px<M>::PX, NT = Px<M>::NT, LS = Px<M>::LS;
+  constexpr int PX = Px<M, V>::PX, NT = Px<M, V>::NT, LS = Px<M, V>::LS;
   const int tid = threadIdx.x, s = blockIdx.x, k = k0 + s;
   const int2 pk = g.pos[k];
   const size_t n = (size_t)g.n;
@@ -819,11 +839,11 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_patch(GradArgs g, int k0) 
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
     int r, c;
-    pix_rc<M>(tid, e, r, c);
+    pix_rc<M, V>(tid, e, r, c);
     A[r * LS + c] = mul(ldT<T>(g.probe, (size_t)r * M + c), ldT<T>(g.obj, (pk.x + r) * n + pk.y + c));
   }
   __syncthreads();
-  fft2_forward<T, M>(A, tws, tid);
+  fft2_forward<T, M, V>(A, tws, tid);
   // residual in Fourier space: Psi - Psi' = (|Psi| - a) Psi/|Psi|, or -a where Psi = 0
   const float* dk = g.dperm + (size_t)k * M * M;
   const T inv_m2 = T(1) / T(M * M);
@@ -831,7 +851,7 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_patch(GradArgs g, int k0) 
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
     int r, c;
-    pix_rc<M>(tid, e, r, c);
+    pix_rc<M, V>(tid, e, r, c);
     const cx<T> P = A[r * LS + c];
     const T amp = sqrt(fmax(T(dk[r * M + c]), T(0)));
     const T mag = sqrt(norm2(P));
@@ -841,12 +861,12 @@ __global__ __launch_bounds__(Plan<M>::NT) void k_grad_patch(GradArgs g, int k0) 
     A[r * LS + c] = scale(E, inv_m2);
   }
   __syncthreads();
-  fft2_inverse<T, M>(A, tws, tid);
+  fft2_inverse<T, M, V>(A, tws, tid);
   const size_t base = (size_t)s * M * M;
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
     int r, c;
-    pix_rc<M>(tid, e, r, c);
+    pix_rc<M, V>(tid, e, r, c);
     const cx<T> ev = A[r * LS + c];
     const cx<T> q = ldT<T>(g.probe, (size_t)r * M + c);
     const cx<T> zz = ldT<T>(g.obj, (pk.x + r) * n + pk.y + c);
@@ -903,7 +923,7 @@ __global__ __launch_bounds__(256) void k_grad_probe(GradArgs g, int cnt, int fir
 // ---------------------------------------------------------------------------
 // init helpers
 // ---------------------------------------------------------------------------
-template <int M>
+template <int M, int V>
 __global__ __launch_bounds__(256) void k_layout(const float* d, float* dperm, double* sums,
                                                 int* bad) {
   __shared__ double redd[16];
@@ -913,7 +933,7 @@ __global__ __launch_bounds__(256) void k_layout(const float* d, float* dperm, do
   double acc = 0.0;
   int nonfinite = 0;
   for (int e = tid; e < M * M; e += 256) {
-    const float v = src[freq_of_pos<M>(e / M) * M + freq_of_pos<M>(e % M)];
+    const float v = src[freq_of_pos<M, V>(e / M) * M + freq_of_pos<M, V>(e % M)];
     dst[e] = v;
     nonfinite |= !isfinite(v);
     acc += (double)v;
@@ -944,233 +964,210 @@ __global__ __launch_bounds__(256) void k_normalize(float2* probe, double dp_avg,
   }
 }
 
-__global__ __launch_bounds__(256) void k_sum_doubles(const double* in, int count, double* out) {
-  __shared__ double redd[16];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < count; i += 256) acc += in[i];
-  const double tot = block_sum<256>(acc, redd, threadIdx.x);
-  if (threadIdx.x == 0) out[0] = tot;
-}
-
-__global__ __launch_bounds__(256) void k_zero_doubles(double* p, int count) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < count) p[i] = 0.0;
-}
-
-__global__ __launch_bounds__(64) void k_zero_u32(unsigned* p) { p[threadIdx.x] = 0u; }
-
-__global__ __launch_bounds__(256) void k_slot_info(const int* idx, const int2* pos, int n_pos,
-                                                   int4* slot, int count) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= count) return;
-  const int k = min(max(idx[j], 0), n_pos - 1);
-  const int2 p = pos[k];
-  slot[j] = make_int4(k, p.x, p.y, 0);
-}
 
 // ---------------------------------------------------------------------------
-// launchers
+// launchers: Launchers<M> (declared in launch.hpp) for one probe side, with
+// run-time plan / level / finalize-shape choice mapped onto instantiations
 // ---------------------------------------------------------------------------
-#define EMG_DISPATCH_M(m, FN, ...)                \
-  switch (m) {                                    \
-    case 32: return FN<32>(__VA_ARGS__);          \
-    case 64: return FN<64>(__VA_ARGS__);          \
-    case 128: return FN<128>(__VA_ARGS__);        \
-    default: return hipErrorInvalidValue;         \
+template <int N>
+using IC = std::integral_constant<int, N>;
+
+template <int M, class Fn>
+hipError_t with_plan(int v, Fn&& fn) {
+  switch (v) {
+    case 0: return fn(IC<0>{});
+    case 1: if constexpr (PlanCount<M>::value > 1) return fn(IC<1>{}); break;
+    case 2: if constexpr (PlanCount<M>::value > 2) return fn(IC<2>{}); break;
+    case 3: if constexpr (PlanCount<M>::value > 3) return fn(IC<3>{}); break;
+    default: break;
   }
-
-#define EMG_DISPATCH_ML(m, L, FN, ...)                                          \
-  switch (m * 4 + L) {                                                          \
-    case 32 * 4 + 1: return FN<32, 1>(__VA_ARGS__);                             \
-    case 32 * 4 + 2: return FN<32, 2>(__VA_ARGS__);                             \
-    case 32 * 4 + 3: return FN<32, 3>(__VA_ARGS__);                             \
-    case 64 * 4 + 1: return FN<64, 1>(__VA_ARGS__);                             \
-    case 64 * 4 + 2: return FN<64, 2>(__VA_ARGS__);                             \
-    case 64 * 4 + 3: return FN<64, 3>(__VA_ARGS__);                             \
-    case 128 * 4 + 1: return FN<128, 1>(__VA_ARGS__);                           \
-    case 128 * 4 + 2: return FN<128, 2>(__VA_ARGS__);                           \
-    case 128 * 4 + 3: return FN<128, 3>(__VA_ARGS__);                           \
-    default: return hipErrorInvalidValue;                                       \
-  }
-
-// With timing events the launch goes through hipExtLaunchKernel, which
-// timestamps the kernel's own execution (the dispatch is not included).
-template <int M, int L>
-static hipError_t patch_step_l(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (e0) {
-    StepArgs aa = a;
-    void* args[] = {&aa};
-    return hipExtLaunchKernel((const void*)k_patch_step<M, L>, dim3(a.b), dim3(Plan<M>::NT), args,
-                              0, s, e0, e1, 0);
-  }
-  hipLaunchKernelGGL((k_patch_step<M, L>), dim3(a.b), dim3(Plan<M>::NT), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_patch_step(int m, int L, const StepArgs& a, hipStream_t s, hipEvent_t e0,
-                             hipEvent_t e1) {
-  EMG_DISPATCH_ML(m, L, patch_step_l, a, s, e0, e1);
+  return hipErrorInvalidValue;
 }
 
-template <int M>
-static hipError_t finalize_l(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  int ntiles;
-  const int items = finalize_items<M, kFinNT>(a.n, &ntiles);
-  if (e0) {
-    StepArgs aa = a;
-    void* args[] = {&aa, &ntiles};
-    return hipExtLaunchKernel((const void*)k_finalize<M>, dim3(items), dim3(kFinNT), args, 0, s, e0,
-                              e1, 0);
-  }
-  hipLaunchKernelGGL(k_finalize<M>, dim3(items), dim3(kFinNT), 0, s, a, ntiles);
-  return hipGetLastError();
-}
-hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  EMG_DISPATCH_M(m, finalize_l, a, s, e0, e1);
-}
-
-template <int M, int L>
-static hipError_t patch_multi_l(const StepArgs* args, const int2* work, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_patch_step_multi<M, L>), dim3(blocks), dim3(Plan<M>::NT), 0, s, args, work);
-  return hipGetLastError();
-}
-hipError_t launch_patch_step_multi(int m, int L, const StepArgs* args, const int2* work, int blocks,
-                                   hipStream_t s) {
-  EMG_DISPATCH_ML(m, L, patch_multi_l, args, work, blocks, s);
-}
-
-template <int M>
-static hipError_t finalize_multi_l(const StepArgs* args, const int2* work, int blocks,
-                                   hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_multi<M>, dim3(blocks), dim3(kFinNT), 0, s, args, work);
-  return hipGetLastError();
-}
-hipError_t launch_finalize_multi(int m, const StepArgs* args, const int2* work, int blocks,
-                                 hipStream_t s) {
-  EMG_DISPATCH_M(m, finalize_multi_l, args, work, blocks, s);
-}
-
-hipError_t finalize_item_count(int m, int n, int* items) {
-  int ntiles = 0;
-  switch (m) {
-    case 32: *items = finalize_items<32, kFinNT>(n, &ntiles); return hipSuccess;
-    case 64: *items = finalize_items<64, kFinNT>(n, &ntiles); return hipSuccess;
-    case 128: *items = finalize_items<128, kFinNT>(n, &ntiles); return hipSuccess;
+template <class Fn>
+hipError_t with_levels(int L, Fn&& fn) {
+  switch (L) {
+    case 1: return fn(IC<1>{});
+    case 2: return fn(IC<2>{});
+    case 3: return fn(IC<3>{});
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int M, int L>
-static hipError_t plain_step_l(const StepArgs& a, hipStream_t s) {
-  constexpr int NT = Plan<M>::NT;
-  hipLaunchKernelGGL(k_probe_prep<M>, dim3(1), dim3(NT), 0, s, a);
-  hipLaunchKernelGGL(k_gather<M>, dim3(a.b), dim3(NT), 0, s, a);
-  hipLaunchKernelGGL((k_fft<M, false>), dim3(a.b), dim3(NT), 0, s, a);
-  hipLaunchKernelGGL(k_project<M>, dim3(a.b), dim3(NT), 0, s, a);
-  hipLaunchKernelGGL((k_fft<M, true>), dim3(a.b), dim3(NT), 0, s, a);
-  hipLaunchKernelGGL((k_numerators<M, L>), dim3(a.b), dim3(NT), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_plain_step(int m, int L, const StepArgs& a, hipStream_t s) {
-  EMG_DISPATCH_ML(m, L, plain_step_l, a, s);
+template <class Fn>
+hipError_t with_fin(int f, Fn&& fn) {
+  switch (f) {
+    case 0: return fn(IC<0>{});
+    case 1: return fn(IC<1>{});
+    case 2: return fn(IC<2>{});
+    case 3: return fn(IC<3>{});
+    default: return hipErrorInvalidValue;
+  }
 }
 
-template <int M, int L>
-static hipError_t grid_l(int num_cus, int* grid) {
-  int per = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_epoch_persistent<M, L>,
-                                                              Plan<M>::NT, 0);
-  if (e != hipSuccess) return e;
-  *grid = per * num_cus;
-  return hipSuccess;
-}
-hipError_t persistent_grid_size(int m, int L, int num_cus, int* grid) {
-  EMG_DISPATCH_ML(m, L, grid_l, num_cus, grid);
-}
-
-template <int M, int L>
-static hipError_t persistent_l(const StepArgs& a, int n_pos, int B, int grid, unsigned* bar,
-                               unsigned bar_base, int* err, int* used_grid, hipStream_t s) {
-  int ntiles;
-  int nitems = finalize_items<M, Plan<M>::NT>(a.n, &ntiles);
-  StepArgs aa = a;
-  const int want = max(min(B, n_pos), nitems);
-  int g = max(1, min(grid, want));
-  *used_grid = g;
-  void* args[] = {&aa, &n_pos, &B, &ntiles, &nitems, &bar, &bar_base, &err};
-  return hipLaunchCooperativeKernel((const void*)k_epoch_persistent<M, L>, dim3(g),
-                                    dim3(Plan<M>::NT), args, 0, s);
-}
-hipError_t launch_persistent_epoch(int m, int L, const StepArgs& a, int n_pos, int minibatch,
-                                   int grid, unsigned* bar, unsigned bar_base, int* err,
-                                   int* used_grid, hipStream_t s) {
-  EMG_DISPATCH_ML(m, L, persistent_l, a, n_pos, minibatch, grid, bar, bar_base, err, used_grid, s);
-}
-
-hipError_t launch_slot_info(const int* idx, const int2* pos, int n_pos, int4* slot, int count,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_slot_info, dim3((count + 255) / 256), dim3(256), 0, s, idx, pos, n_pos, slot,
-                     count);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero_u32(unsigned* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, p);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero_doubles(double* p, int count, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_doubles, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
-  return hipGetLastError();
-}
-
-hipError_t launch_sum_doubles(const double* in, int count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_doubles, dim3(1), dim3(256), 0, s, in, count, out);
-  return hipGetLastError();
+// With timing events the launch goes through hipExtLaunchKernel, which
+// timestamps the kernel's own execution (the dispatch is not included).
+template <int M>
+hipError_t Launchers<M>::patch_step(int v, int L, const StepArgs& a, hipStream_t s, hipEvent_t e0,
+                                    hipEvent_t e1) {
+  return with_plan<M>(v, [&](auto vc) {
+    return with_levels(L, [&](auto lc) {
+      constexpr int V = decltype(vc)::value, LV = decltype(lc)::value, NT = Plan<M, V>::NT;
+      if (e0) {
+        StepArgs aa = a;
+        void* args[] = {&aa};
+        return hipExtLaunchKernel((const void*)k_patch_step<M, V, LV>, dim3(a.b), dim3(NT), args,
+                                  0, s, e0, e1, 0);
+      }
+      hipLaunchKernelGGL((k_patch_step<M, V, LV>), dim3(a.b), dim3(NT), 0, s, a);
+      return hipGetLastError();
+    });
+  });
 }
 
 template <int M>
-static hipError_t layout_l(const float* d, float* dperm, int n_pos, double* sums, int* bad,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_layout<M>, dim3(n_pos), dim3(256), 0, s, d, dperm, sums, bad);
-  return hipGetLastError();
-}
-hipError_t launch_layout_intensities(int m, const float* d, float* dperm, int n_pos,
-                                     double* pattern_sums, int* bad_flag, hipStream_t s) {
-  EMG_DISPATCH_M(m, layout_l, d, dperm, n_pos, pattern_sums, bad_flag, s);
+hipError_t Launchers<M>::finalize(int f, const StepArgs& a, hipStream_t s, hipEvent_t e0,
+                                  hipEvent_t e1) {
+  return with_fin(f, [&](auto fc) {
+    constexpr int F = decltype(fc)::value, FNT = FinShape<F>::FNT, T = FinShape<F>::T;
+    int ntiles;
+    const int items = finalize_items<M, FNT, T>(a.n, &ntiles);
+    if (e0) {
+      StepArgs aa = a;
+      void* args[] = {&aa, &ntiles};
+      return hipExtLaunchKernel((const void*)k_finalize<M, F>, dim3(items), dim3(FNT), args, 0, s,
+                                e0, e1, 0);
+    }
+    hipLaunchKernelGGL((k_finalize<M, F>), dim3(items), dim3(FNT), 0, s, a, ntiles);
+    return hipGetLastError();
+  });
 }
 
 template <int M>
-static hipError_t normalize_l(float2* probe, double dp_avg, int* flag, hipStream_t s) {
+hipError_t Launchers<M>::patch_step_multi(int v, int L, const StepArgs* args, const int2* work,
+                                          int blocks, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    return with_levels(L, [&](auto lc) {
+      constexpr int V = decltype(vc)::value, LV = decltype(lc)::value;
+      hipLaunchKernelGGL((k_patch_step_multi<M, V, LV>), dim3(blocks), dim3(Plan<M, V>::NT), 0, s,
+                         args, work);
+      return hipGetLastError();
+    });
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::finalize_multi(int f, const StepArgs* args, const int2* work, int blocks,
+                                        hipStream_t s) {
+  return with_fin(f, [&](auto fc) {
+    constexpr int F = decltype(fc)::value;
+    hipLaunchKernelGGL((k_finalize_multi<M, F>), dim3(blocks), dim3(FinShape<F>::FNT), 0, s, args,
+                       work);
+    return hipGetLastError();
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::finalize_item_count(int f, int n, int* items) {
+  return with_fin(f, [&](auto fc) {
+    constexpr int F = decltype(fc)::value;
+    int ntiles = 0;
+    *items = finalize_items<M, FinShape<F>::FNT, FinShape<F>::T>(n, &ntiles);
+    return hipSuccess;
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::plain_step(int v, int L, const StepArgs& a, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    return with_levels(L, [&](auto lc) {
+      constexpr int V = decltype(vc)::value, LV = decltype(lc)::value, NT = Plan<M, V>::NT;
+      hipLaunchKernelGGL((k_probe_prep<M, V>), dim3(1), dim3(NT), 0, s, a);
+      hipLaunchKernelGGL((k_gather<M, V>), dim3(a.b), dim3(NT), 0, s, a);
+      hipLaunchKernelGGL((k_fft<M, V, false>), dim3(a.b), dim3(NT), 0, s, a);
+      hipLaunchKernelGGL((k_project<M, V>), dim3(a.b), dim3(NT), 0, s, a);
+      hipLaunchKernelGGL((k_fft<M, V, true>), dim3(a.b), dim3(NT), 0, s, a);
+      hipLaunchKernelGGL((k_numerators<M, V, LV>), dim3(a.b), dim3(NT), 0, s, a);
+      return hipGetLastError();
+    });
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::persistent_grid_size(int v, int L, int num_cus, int* grid) {
+  return with_plan<M>(v, [&](auto vc) {
+    return with_levels(L, [&](auto lc) {
+      constexpr int V = decltype(vc)::value, LV = decltype(lc)::value;
+      int per = 0;
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, k_epoch_persistent<M, V, LV>, Plan<M, V>::NT, 0);
+      if (e != hipSuccess) return e;
+      *grid = per * num_cus;
+      return hipSuccess;
+    });
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::persistent_epoch(int v, int L, const StepArgs& a, int n_pos, int B,
+                                          int grid, unsigned* bar, unsigned bar_base, int* err,
+                                          int* used_grid, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    return with_levels(L, [&](auto lc) {
+      constexpr int V = decltype(vc)::value, LV = decltype(lc)::value, NT = Plan<M, V>::NT;
+      int ntiles;
+      int nitems = finalize_items<M, NT, PersistFin<NT>::T>(a.n, &ntiles);
+      StepArgs aa = a;
+      int np = n_pos, bb = B;
+      unsigned* br = bar;
+      unsigned bb0 = bar_base;
+      int* er = err;
+      const int want = max(min(B, n_pos), nitems);
+      const int g = max(1, min(grid, want));
+      *used_grid = g;
+      void* args[] = {&aa, &np, &bb, &ntiles, &nitems, &br, &bb0, &er};
+      return hipLaunchCooperativeKernel((const void*)k_epoch_persistent<M, V, LV>, dim3(g),
+                                        dim3(NT), args, 0, s);
+    });
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::layout(int v, const float* d, float* dperm, int n_pos, double* sums,
+                                int* bad, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    constexpr int V = decltype(vc)::value;
+    hipLaunchKernelGGL((k_layout<M, V>), dim3(n_pos), dim3(256), 0, s, d, dperm, sums, bad);
+    return hipGetLastError();
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::normalize(float2* probe, double dp_avg, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_normalize<M>, dim3(1), dim3(256), 0, s, probe, dp_avg, flag);
   return hipGetLastError();
 }
-hipError_t launch_normalize_probe(int m, float2* probe, double dp_avg, int* zero_flag,
-                                  hipStream_t s) {
-  EMG_DISPATCH_M(m, normalize_l, probe, dp_avg, zero_flag, s);
-}
 
 template <int M>
-static hipError_t misfit_l(const float2* obj, int n, const float2* probe, const float* dperm,
-                           const int2* pos, int n_pos, const float2* tw, double* phi_all,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_misfit<M>, dim3(n_pos), dim3(Plan<M>::NT), 0, s, obj, n, probe, dperm, pos,
-                     tw, phi_all);
-  return hipGetLastError();
-}
-hipError_t launch_misfit_terms(int m, const float2* obj, int n, const float2* probe,
-                               const float* dperm, const int2* pos, int n_pos, const float2* tw,
-                               double* phi_all, hipStream_t s) {
-  EMG_DISPATCH_M(m, misfit_l, obj, n, probe, dperm, pos, n_pos, tw, phi_all, s);
+hipError_t Launchers<M>::misfit(int v, const float2* obj, int n, const float2* probe,
+                                const float* dperm, const int2* pos, int n_pos, const float2* tw,
+                                double* phi_all, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    constexpr int V = decltype(vc)::value;
+    hipLaunchKernelGGL((k_misfit<M, V>), dim3(n_pos), dim3(Plan<M, V>::NT), 0, s, obj, n, probe,
+                       dperm, pos, tw, phi_all);
+    return hipGetLastError();
+  });
 }
 
-template <typename T, int M>
+template <typename T, int M, int V>
 static hipError_t grad_t(const GradArgs& g, hipStream_t s) {
-  constexpr int NT = Plan<M>::NT, TS = 32;
+  constexpr int NT = Plan<M, V>::NT, TS = 32;
   const int tpr = (g.n + TS - 1) / TS;
   for (int k0 = 0; k0 < g.n_pos; k0 += g.chunk) {
     const int cnt = min(g.chunk, g.n_pos - k0);
     const int first = k0 == 0;
-    hipLaunchKernelGGL((k_grad_patch<T, M>), dim3(cnt), dim3(NT), 0, s, g, k0);
+    hipLaunchKernelGGL((k_grad_patch<T, M, V>), dim3(cnt), dim3(NT), 0, s, g, k0);
     hipLaunchKernelGGL((k_grad_scatter<T, M>), dim3(tpr * tpr), dim3(256), 0, s, g, k0, cnt, first);
     hipLaunchKernelGGL((k_grad_probe<T, M>), dim3((M * M + 255) / 256), dim3(256), 0, s, g, cnt,
                        first);
@@ -1179,20 +1176,17 @@ static hipError_t grad_t(const GradArgs& g, hipStream_t s) {
   }
   return hipSuccess;
 }
-hipError_t launch_grad(int m, bool f64, const GradArgs& g, hipStream_t s) {
-  if (f64) {
-    switch (m) {
-      case 32: return grad_t<double, 32>(g, s);
-      case 64: return grad_t<double, 64>(g, s);
-      default: return hipErrorInvalidValue;
+
+template <int M>
+hipError_t Launchers<M>::grad(int v, bool f64, const GradArgs& g, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    constexpr int V = decltype(vc)::value;
+    if (f64) {
+      if constexpr (M <= 64) return grad_t<double, M, V>(g, s);
+      return hipErrorInvalidValue;
     }
-  }
-  switch (m) {
-    case 32: return grad_t<float, 32>(g, s);
-    case 64: return grad_t<float, 64>(g, s);
-    case 128: return grad_t<float, 128>(g, s);
-    default: return hipErrorInvalidValue;
-  }
+    return grad_t<float, M, V>(g, s);
+  });
 }
 
 }  // namespace emg

@@ -1,4 +1,4 @@
-// Host-side launchers for the eMAGPIE kernels (implemented in kernels.hip).
+// Host-side launchers for the eMAGPIE kernels (kernels.hpp, kernels_common.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,29 +38,32 @@ struct StepArgs {
   float* qqmax;      // 1
 };
 
+// Kernel plans: v = FFT plan variant, f = finalize shape (plans.hpp).  The
+// variant must be the one the intensities were laid out with.
+
 // e0 / e1 (optional): events timestamped at the kernel's start and end
-hipError_t launch_patch_step(int m, int L, const StepArgs& a, hipStream_t s,
+hipError_t launch_patch_step(int m, int v, int L, const StepArgs& a, hipStream_t s,
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-hipError_t launch_finalize(int m, const StepArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+hipError_t launch_finalize(int m, int f, const StepArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
 // Many instances per launch: block b runs work[b] = (record in args, slot) for
 // the patch stage, or (record in args, finalize item) for the finalize.
-hipError_t launch_patch_step_multi(int m, int L, const StepArgs* args, const int2* work, int blocks,
-                                   hipStream_t s);
-hipError_t launch_finalize_multi(int m, const StepArgs* args, const int2* work, int blocks,
+hipError_t launch_patch_step_multi(int m, int v, int L, const StepArgs* args, const int2* work,
+                                   int blocks, hipStream_t s);
+hipError_t launch_finalize_multi(int m, int f, const StepArgs* args, const int2* work, int blocks,
                                  hipStream_t s);
 // number of finalize work items (object tiles + probe units) for an n x n object
-hipError_t finalize_item_count(int m, int n, int* items);
+hipError_t finalize_item_count(int m, int f, int n, int* items);
 
 // plain path: the six patch-stage kernels (finalize is launched separately)
-hipError_t launch_plain_step(int m, int L, const StepArgs& a, hipStream_t s);
+hipError_t launch_plain_step(int m, int v, int L, const StepArgs& a, hipStream_t s);
 
 // Persistent epoch: one cooperative launch runs every minibatch of a sweep.
 // a.slot must point at the slot list of the whole sweep (N entries); a.b is ignored.
 // `bar` is a device counter that only grows: the kernel's barriers wait for
 // bar_base + (i + 1) * grid arrivals; `err` is set if a barrier wait gives up.
-hipError_t persistent_grid_size(int m, int L, int num_cus, int* grid);
-hipError_t launch_persistent_epoch(int m, int L, const StepArgs& a, int n_pos, int minibatch,
+hipError_t persistent_grid_size(int m, int v, int L, int num_cus, int* grid);
+hipError_t launch_persistent_epoch(int m, int v, int L, const StepArgs& a, int n_pos, int minibatch,
                                    int grid, unsigned* bar, unsigned bar_base, int* err,
                                    int* used_grid, hipStream_t s);
 // zero 64 consecutive unsigned counters
@@ -75,10 +78,12 @@ hipError_t launch_slot_info(const int* idx, const int2* pos, int n_pos, int4* sl
 hipError_t launch_zero_doubles(double* p, int count, hipStream_t s);
 // out[0] = sum_{i < count} in[i] in a fixed order
 hipError_t launch_sum_doubles(const double* in, int count, double* out, hipStream_t s);
+// p[i] = v for i < count
+hipError_t launch_fill_c64(float2* p, size_t count, float2 v, hipStream_t s);
 
-// Copy intensities into transform order, flag non-finite values, and write
-// per-pattern float64 sums.
-hipError_t launch_layout_intensities(int m, const float* d, float* dperm, int n_pos,
+// Copy intensities into the transform order of plan v, flag non-finite
+// values, and write per-pattern float64 sums.
+hipError_t launch_layout_intensities(int m, int v, const float* d, float* dperm, int n_pos,
                                      double* pattern_sums, int* bad_flag, hipStream_t s);
 
 // probe <- probe * dp_avg / ||probe||; flag when the norm is zero
@@ -86,7 +91,7 @@ hipError_t launch_normalize_probe(int m, float2* probe, double dp_avg, int* zero
                                   hipStream_t s);
 
 // misfit terms of all patterns -> phi_all (N doubles), unreduced
-hipError_t launch_misfit_terms(int m, const float2* obj, int n, const float2* probe,
+hipError_t launch_misfit_terms(int m, int v, const float2* obj, int n, const float2* probe,
                                const float* dperm, const int2* pos, int n_pos, const float2* tw,
                                double* phi_all, hipStream_t s);
 
@@ -106,6 +111,32 @@ struct GradArgs {
   void* gq_slots;      // chunk x m^2
   double* phi_all;     // N
 };
-hipError_t launch_grad(int m, bool f64, const GradArgs& g, hipStream_t s);
+hipError_t launch_grad(int m, int v, bool f64, const GradArgs& g, hipStream_t s);
+
+// The launchers of one probe side (kernels.hpp; instantiated per side in
+// kernels_m32.hip, kernels_m64.hip and kernels_m128.hip).
+template <int M>
+struct Launchers {
+  static hipError_t patch_step(int v, int L, const StepArgs& a, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1);
+  static hipError_t finalize(int f, const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+  static hipError_t patch_step_multi(int v, int L, const StepArgs* args, const int2* work,
+                                     int blocks, hipStream_t s);
+  static hipError_t finalize_multi(int f, const StepArgs* args, const int2* work, int blocks,
+                                   hipStream_t s);
+  static hipError_t finalize_item_count(int f, int n, int* items);
+  static hipError_t plain_step(int v, int L, const StepArgs& a, hipStream_t s);
+  static hipError_t persistent_grid_size(int v, int L, int num_cus, int* grid);
+  static hipError_t persistent_epoch(int v, int L, const StepArgs& a, int n_pos, int B, int grid,
+                                     unsigned* bar, unsigned bar_base, int* err, int* used_grid,
+                                     hipStream_t s);
+  static hipError_t layout(int v, const float* d, float* dperm, int n_pos, double* sums, int* bad,
+                           hipStream_t s);
+  static hipError_t normalize(float2* probe, double dp_avg, int* flag, hipStream_t s);
+  static hipError_t misfit(int v, const float2* obj, int n, const float2* probe, const float* dperm,
+                           const int2* pos, int n_pos, const float2* tw, double* phi_all,
+                           hipStream_t s);
+  static hipError_t grad(int v, bool f64, const GradArgs& g, hipStream_t s);
+};
 
 }  // namespace emg

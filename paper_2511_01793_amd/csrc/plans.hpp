@@ -1,0 +1,73 @@
+// Shape variants the kernels are instantiated for, shared by device and host
+// code.  The autotuner in api.hip times them on the caller's data and picks
+// one per context.
+//
+// FFT plan (m, variant): the 1-D length-m transform is split as m = R1 * R2
+// (pass 1: R2-point DFTs over stride-R1 elements, pass 2: R1-point DFTs over
+// contiguous runs), computed by NT threads per patch.  Each thread owns
+// m^2 / (4 NT) 2 x 2 pixel blocks in the per-pixel phases.  Variant 0 is the
+// default.  Plans with the same (R1, R2) give bitwise-identical results;
+// another split reorders the DFT arithmetic (same transform, other rounding)
+// and lays the intensities out in its own transform order.
+//
+// Finalize shape (variant): FNT threads per work item, object tiles of
+// T x T pixels.  Every shape sums the same terms in the same order, so the
+// results are bitwise identical; only the speed differs.
+#pragma once
+
+namespace emg {
+
+template <int M, int V> struct Plan;
+template <> struct Plan<32, 0> { static constexpr int R1 = 8, R2 = 4, NT = 256; };
+template <> struct Plan<32, 1> { static constexpr int R1 = 4, R2 = 8, NT = 256; };
+template <> struct Plan<64, 0> { static constexpr int R1 = 8, R2 = 8, NT = 1024; };
+template <> struct Plan<64, 1> { static constexpr int R1 = 16, R2 = 4, NT = 1024; };
+template <> struct Plan<64, 2> { static constexpr int R1 = 4, R2 = 16, NT = 1024; };
+template <> struct Plan<64, 3> { static constexpr int R1 = 8, R2 = 8, NT = 512; };
+template <> struct Plan<128, 0> { static constexpr int R1 = 16, R2 = 8, NT = 1024; };
+template <> struct Plan<128, 1> { static constexpr int R1 = 8, R2 = 16, NT = 1024; };
+template <> struct Plan<128, 2> { static constexpr int R1 = 16, R2 = 8, NT = 512; };
+
+template <int M> struct PlanCount;
+template <> struct PlanCount<32> { static constexpr int value = 2; };
+template <> struct PlanCount<64> { static constexpr int value = 4; };
+template <> struct PlanCount<128> { static constexpr int value = 3; };
+
+constexpr int kMaxFftPlans = 4;
+
+// host-side description of FFT plan (m, v); false if there is no such plan
+inline bool fft_plan_desc(int m, int v, int* r1, int* r2, int* nt) {
+  struct D {
+    int m, v, r1, r2, nt;
+  };
+  static const D t[] = {{32, 0, 8, 4, 256},   {32, 1, 4, 8, 256},   {64, 0, 8, 8, 1024},
+                        {64, 1, 16, 4, 1024}, {64, 2, 4, 16, 1024}, {64, 3, 8, 8, 512},
+                        {128, 0, 16, 8, 1024}, {128, 1, 8, 16, 1024}, {128, 2, 16, 8, 512}};
+  for (const D& d : t)
+    if (d.m == m && d.v == v) {
+      *r1 = d.r1;
+      *r2 = d.r2;
+      *nt = d.nt;
+      return true;
+    }
+  return false;
+}
+inline int fft_plan_count(int m) { return m == 32 ? 2 : m == 64 ? 4 : m == 128 ? 3 : 0; }
+
+// finalize shapes: (threads per item, object tile side)
+template <int F> struct FinShape;
+template <> struct FinShape<0> { static constexpr int FNT = 256, T = 32; };
+template <> struct FinShape<1> { static constexpr int FNT = 256, T = 16; };
+template <> struct FinShape<2> { static constexpr int FNT = 512, T = 32; };
+template <> struct FinShape<3> { static constexpr int FNT = 1024, T = 64; };
+constexpr int kFinShapes = 4;
+
+inline bool fin_shape_desc(int f, int* fnt, int* tile) {
+  static const int t[kFinShapes][2] = {{256, 32}, {256, 16}, {512, 32}, {1024, 64}};
+  if (f < 0 || f >= kFinShapes) return false;
+  *fnt = t[f][0];
+  *tile = t[f][1];
+  return true;
+}
+
+}  // namespace emg

@@ -16,7 +16,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libemagpie.so")
 
-PATHS = {"plain": 0, "fused": 1, "graph": 2, "persistent": 3}
+PATHS = {"plain": 0, "fused": 1, "graph": 2, "persistent": 3, "auto": 4}
+PATH_NAMES = {v: k for k, v in PATHS.items()}
+TUNE = -1  # fft_plan / finalize_shape: choose by timing at init
 F32, F64 = 0, 1
 
 STATUS = {
@@ -30,7 +32,7 @@ EXPORTS = [
     "emagpie_misfit", "emagpie_grad", "emagpie_permutation", "emagpie_last_error",
     "emagpie_version", "emagpie_profile_enable", "emagpie_profile_read",
     "emagpie_group_workspace_size", "emagpie_group_create", "emagpie_group_epoch",
-    "emagpie_group_destroy",
+    "emagpie_group_destroy", "emagpie_plan_get", "emagpie_plan_describe",
 ]
 
 
@@ -47,8 +49,29 @@ class Config(ctypes.Structure):
         ("minibatch", ctypes.c_int32), ("levels", ctypes.c_int32),
         ("alpha", ctypes.c_float), ("alpha_z", ctypes.c_float),
         ("update_probe", ctypes.c_int32), ("joint_step", ctypes.c_int32), ("path", ctypes.c_int32),
-        ("seed", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64), ("fft_plan", ctypes.c_int32), ("finalize_shape", ctypes.c_int32),
+        ("tune_cache", ctypes.c_char_p),
     ]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [
+        ("fft_plan", ctypes.c_int32), ("r1", ctypes.c_int32), ("r2", ctypes.c_int32),
+        ("threads", ctypes.c_int32), ("finalize_shape", ctypes.c_int32),
+        ("fin_threads", ctypes.c_int32), ("fin_tile", ctypes.c_int32), ("path", ctypes.c_int32),
+        ("tuned", ctypes.c_int32), ("n_fft_plans", ctypes.c_int32), ("fft_us", ctypes.c_float * 4),
+        ("n_fin_shapes", ctypes.c_int32), ("fin_us", ctypes.c_float * 4),
+        ("path_ms", ctypes.c_float * 4),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.endswith(("_us", "_ms"))}
+        d["fft_us"] = list(self.fft_us)[:self.n_fft_plans]
+        d["fin_us"] = list(self.fin_us)[:self.n_fin_shapes]
+        d["path_ms"] = {PATH_NAMES[i]: t for i, t in enumerate(self.path_ms) if t >= 0}
+        d["path"] = PATH_NAMES.get(self.path, self.path)
+        d["tuned"] = {0: "fixed", 1: "timed", 2: "cache"}.get(self.tuned, self.tuned)
+        return d
 
 
 _lib = None
@@ -84,6 +107,8 @@ def lib() -> ctypes.CDLL:
         "emagpie_group_create": [ctypes.POINTER(vp), i32, vp, vp, sz, vp],
         "emagpie_group_epoch": [vp, vp, vp, i64, vp, vp],
         "emagpie_group_destroy": [vp],
+        "emagpie_plan_get": [vp, ctypes.POINTER(Plan)],
+        "emagpie_plan_describe": [i32, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -123,6 +148,16 @@ def permutation(seed: int, epoch: int, n: int) -> np.ndarray:
     return out
 
 
+def plan_describe(m: int, fft_plan: int = 0, finalize_shape: int = 0) -> dict:
+    """Shape of FFT plan `fft_plan` and finalize shape `finalize_shape` for probe side m (host)."""
+    p, cnt = Plan(), ctypes.c_int32(0)
+    _check(lib().emagpie_plan_describe(m, fft_plan, finalize_shape, ctypes.byref(p), ctypes.byref(cnt)))
+    d = {k: getattr(p, k) for k in ("fft_plan", "r1", "r2", "threads", "finalize_shape",
+                                    "fin_threads", "fin_tile")}
+    d["fft_plans"] = cnt.value
+    return d
+
+
 def _expect(t: torch.Tensor, dtype, shape, name):
     if not isinstance(t, torch.Tensor) or t.dtype != dtype or tuple(t.shape) != tuple(shape) \
             or not t.is_cuda or not t.is_contiguous():
@@ -140,7 +175,8 @@ class Reconstruction:
     def __init__(self, positions, intensities: torch.Tensor, n: int, *, minibatch: int,
                  levels: int = 1, alpha: float = 0.05, alpha_z: float = 1.0,
                  update_probe: bool = True, joint_step: bool = True, path: str = "graph",
-                 seed: int = 0):
+                 seed: int = 0, fft_plan: int = 0, finalize_shape: int = 0,
+                 tune_cache: str | None = None):
         pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(-1, 2))
         if intensities.dim() != 3 or intensities.dtype != torch.float32 or not intensities.is_cuda:
             raise ValueError("intensities must be a (N, m, m) float32 CUDA tensor")
@@ -153,7 +189,9 @@ class Reconstruction:
                           levels=int(levels), alpha=float(alpha), alpha_z=float(alpha_z),
                           update_probe=int(bool(update_probe)), joint_step=int(bool(joint_step)),
                           path=PATHS[path],
-                          seed=int(seed) & ((1 << 64) - 1))
+                          seed=int(seed) & ((1 << 64) - 1), fft_plan=int(fft_plan),
+                          finalize_shape=int(finalize_shape),
+                          tune_cache=None if tune_cache is None else os.fsencode(tune_cache))
         nbytes = workspace_size(self.cfg)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=intensities.device)
         base = self._ws.data_ptr()
@@ -193,6 +231,13 @@ class Reconstruction:
         out = ctypes.c_double(0)
         _check(lib().emagpie_dp_avg(self._ctx, ctypes.byref(out)))
         return out.value
+
+    @property
+    def plan(self) -> dict:
+        """The kernel plan this context runs with (after any autotuning at init)."""
+        p = Plan()
+        _check(lib().emagpie_plan_get(self._ctx, ctypes.byref(p)))
+        return p.as_dict()
 
     def _state(self, obj, probe, dtype=torch.complex64):
         _expect(obj, dtype, (self.n, self.n), "object")

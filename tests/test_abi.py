@@ -91,3 +91,38 @@ def test_init_rejects_bad_workspace():
 def test_library_permutation_equals_oracle_bit_exactly():
     for seed, epoch, n in [(0, 0, 1), (1, 0, 2), (1234567, 3, 100), (2**63 + 5, 99, 1600), (42, 7, 10000)]:
         np.testing.assert_array_equal(E.permutation(seed, epoch, n), O.permutation(seed, epoch, n))
+
+
+@pytest.mark.parametrize("m", [32, 64, 128])
+def test_plan_descriptions_are_consistent(m):
+    d0 = E.plan_describe(m, 0, 0)
+    count = d0["fft_plans"]
+    assert count >= 2
+    splits = set()
+    for v in range(count):
+        for f in range(4):
+            d = E.plan_describe(m, v, f)
+            assert d["r1"] * d["r2"] == m and d["r1"] in (4, 8, 16) and d["r2"] in (4, 8, 16)
+            assert d["threads"] in (256, 512, 1024) and (m * m) % (4 * d["threads"]) == 0
+            assert d["fin_tile"] ** 2 % d["fin_threads"] == 0 and d["fin_threads"] % 256 == 0
+        splits.add((d["r1"], d["r2"]))
+    assert len(splits) >= 2  # at least two radix splits to choose from
+    for bad_v, bad_f in [(count, 0), (-1, 0), (0, 4), (0, -1)]:
+        with pytest.raises(E.EmagpieError) as ei:
+            E.plan_describe(m, bad_v, bad_f)
+        assert ei.value.name == "E_ARG"
+
+
+@pytest.mark.parametrize("bad", [dict(fft_plan=9), dict(fft_plan=-2), dict(finalize_shape=4),
+                                 dict(finalize_shape=-3), dict(path=5), dict(m=32, fft_plan=2)])
+def test_plan_config_validation(bad):
+    with pytest.raises(E.EmagpieError) as ei:
+        E.workspace_size(cfg(**bad))
+    assert ei.value.name == "E_ARG"
+
+
+def test_tuning_needs_scratch_state_in_the_workspace():
+    plain = E.workspace_size(cfg(n=256))
+    tuned = E.workspace_size(cfg(n=256, fft_plan=E.TUNE))
+    auto = E.workspace_size(cfg(n=256, path=E.PATHS["auto"]))
+    assert tuned == auto >= plain + 256 * 256 * 8
