@@ -185,6 +185,23 @@ emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void
                                 const int32_t* batch_idx_dev, int32_t b, void* zplus_dev,
                                 void* stream);
 
+/*
+ * Descent check of one minibatch update (the quadratic surrogate of Eq. 3 and
+ * the sampled objective agreement and majorisation of Prop. 3.1).  Applies the
+ * same update as emagpie_step_minibatch to obj_dev / probe_dev (in place; the
+ * result is bitwise identical) and writes three float64 values to out3_dev:
+ *   [0] Phi_B before the step (= the surrogate there, objective agreement),
+ *   [1] surrogate after the step, 1/2 sum_k ||Q' . z'_k - R_k||^2 with the
+ *       revised waves R_k frozen at the state before the step,
+ *   [2] Phi_B after the step (<= [1] by majorisation).
+ * Prop. 3.2 guarantees [1] <= [0] for b = 1 and levels = 1.  Each value is an
+ * FP64 sum, in a fixed order, of terms formed from FP32 state.  Uses the
+ * plain-path kernels plus two reductions; it is meant for checking, not speed.
+ */
+emagpie_status emagpie_check_step(emagpie_ctx ctx, void* obj_dev, void* probe_dev,
+                                  const int32_t* batch_idx_dev, int32_t b, double* out3_dev,
+                                  void* stream);
+
 /* Exit-wave misfit Phi(Q, z) of Eq. 1 over all N positions, float64 sum, to misfit_dev. */
 emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
                               double* misfit_dev, void* stream);

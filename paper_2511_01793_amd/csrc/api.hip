@@ -850,14 +850,41 @@ emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void
   return EMAGPIE_OK;
 }
 
+emagpie_status emagpie_check_step(emagpie_ctx ctx, void* obj_dev, void* probe_dev,
+                                  const int32_t* batch_idx_dev, int32_t b, double* out3_dev,
+                                  void* stream) {
+  if (!ctx || !obj_dev || !probe_dev || !batch_idx_dev || !out3_dev)
+    return fail(EMAGPIE_E_ARG, "null argument");
+  if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int m = ctx->cfg.m, v = ctx->cfg.fft_plan;
+  EMG_HIP(emg::launch_slot_info(batch_idx_dev, ctx->pos, ctx->cfg.n_pos, ctx->slots, b, s));
+  emg::StepArgs a = base_args(ctx, obj_dev, probe_dev);
+  a.slot = ctx->slots;
+  a.b = b;
+  a.sampled = out3_dev;  // [0] accumulates sum_k Phi_k at the state before the step
+  EMG_HIP(emg::launch_zero_doubles(out3_dev, 3, s));
+  // revised waves R_k frozen at the current iterate (kept in the stack buffer), the step
+  EMG_HIP(emg::launch_revised_waves(m, v, a, s));
+  EMG_HIP(emg::launch_numerators(m, v, ctx->cfg.levels, a, s));
+  EMG_HIP(emg::launch_finalize(m, ctx->cfg.finalize_shape, a, s));
+  // [1] surrogate of Eq. 3 at the new state against the frozen R_k, [2] Phi_B at the new state
+  EMG_HIP(emg::launch_surrogate_terms(m, v, a, ctx->phi, s));
+  EMG_HIP(emg::launch_sum_doubles(ctx->phi, b, out3_dev + 1, s));
+  EMG_HIP(emg::launch_misfit_terms(m, v, static_cast<const float2*>(obj_dev), ctx->cfg.n,
+                                   static_cast<const float2*>(probe_dev), ctx->dperm, ctx->pos,
+                                   ctx->slots, b, ctx->tw32, ctx->phi, s));
+  EMG_HIP(emg::launch_sum_doubles(ctx->phi, b, out3_dev + 2, s));
+  return EMAGPIE_OK;
+}
+
 emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
                               double* misfit_dev, void* stream) {
   if (!ctx || !obj_dev || !probe_dev || !misfit_dev) return fail(EMAGPIE_E_ARG, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   EMG_HIP(emg::launch_misfit_terms(ctx->cfg.m, ctx->cfg.fft_plan, static_cast<const float2*>(obj_dev),
-                                   ctx->cfg.n,
-                                   static_cast<const float2*>(probe_dev), ctx->dperm, ctx->pos,
-                                   ctx->cfg.n_pos, ctx->tw32, ctx->phi_all, s));
+                                   ctx->cfg.n, static_cast<const float2*>(probe_dev), ctx->dperm,
+                                   ctx->pos, nullptr, ctx->cfg.n_pos, ctx->tw32, ctx->phi_all, s));
   EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
   return EMAGPIE_OK;
 }

@@ -786,14 +786,16 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_numerators(StepArgs a) {
 template <int M, int V>
 __global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, int n,
                                                         const float2* probe, const float* dperm,
-                                                        const int2* pos, const float2* tw,
-                                                        double* phi_all) {
+                                                        const int2* pos, const int4* slot,
+                                                        const float2* tw, double* phi_all) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ double redd[16];
   constexpr int PX = Px<M, V>::PX, NT = Px<M, V>::NT, LS = Px<M, V>::LS;
-  const int tid = threadIdx.x, k = blockIdx.x;
-  const int2 pk = pos[k];
+  // all patterns (slot == nullptr: block k is pattern k) or the patterns of a slot list
+  const int tid = threadIdx.x;
+  const int k = slot ? slot[blockIdx.x].x : (int)blockIdx.x;
+  const int2 pk = slot ? make_int2(slot[blockIdx.x].y, slot[blockIdx.x].z) : pos[k];
   const float* dk = dperm + (size_t)k * M * M;
   stage_twiddles<M, NT>(tw, tws, tid);
   float dv[PX];
@@ -814,7 +816,31 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, 
     acc += (double)project_px<M>(A[r * LS + c], dv[e]);
   }
   const double tot = block_sum<NT>(acc, redd, tid);
-  if (tid == 0) phi_all[k] = tot / (2.0 * M * M);
+  if (tid == 0) phi_all[blockIdx.x] = tot / (2.0 * M * M);
+}
+
+// Quadratic surrogate of Eq. 3 for the slots of a batch: 1/2 ||Q . z_k - R_k||^2 with the
+// current state (Q, z) and revised exit waves R_k held in a.stack (frozen at an earlier
+// iterate).  FP32 differences, FP64 sum of their squared magnitudes.
+template <int M, int V>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_surrogate(StepArgs a, double* terms) {
+  __shared__ double redd[16];
+  constexpr int PX = Px<M, V>::PX, NT = Px<M, V>::NT;
+  const int tid = threadIdx.x, s = blockIdx.x;
+  const int4 sl = a.slot[s];
+  const float2* zwin = a.obj + (size_t)sl.y * a.n + sl.z;
+  const float2* Rg = a.stack + (size_t)s * M * M;
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < PX; ++e) {
+    int r, c;
+    pix_rc<M, V>(tid, e, r, c);
+    const cx<float> d = sub(mul(ld(a.probe, (size_t)r * M + c), ld(zwin, (size_t)r * a.n + c)),
+                            ld(Rg, (size_t)r * M + c));
+    acc += (double)d.re * (double)d.re + (double)d.im * (double)d.im;
+  }
+  const double tot = block_sum<NT>(acc, redd, tid);
+  if (tid == 0) terms[s] = 0.5 * tot;
 }
 
 template <typename T>
@@ -1150,13 +1176,46 @@ hipError_t Launchers<M>::normalize(float2* probe, double dp_avg, int* flag, hipS
 
 template <int M>
 hipError_t Launchers<M>::misfit(int v, const float2* obj, int n, const float2* probe,
-                                const float* dperm, const int2* pos, int n_pos, const float2* tw,
-                                double* phi_all, hipStream_t s) {
+                                const float* dperm, const int2* pos, const int4* slot, int count,
+                                const float2* tw, double* phi_out, hipStream_t s) {
   return with_plan<M>(v, [&](auto vc) {
     constexpr int V = decltype(vc)::value;
-    hipLaunchKernelGGL((k_misfit<M, V>), dim3(n_pos), dim3(Plan<M, V>::NT), 0, s, obj, n, probe,
-                       dperm, pos, tw, phi_all);
+    hipLaunchKernelGGL((k_misfit<M, V>), dim3(count), dim3(Plan<M, V>::NT), 0, s, obj, n, probe,
+                       dperm, pos, slot, tw, phi_out);
     return hipGetLastError();
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::surrogate(int v, const StepArgs& a, double* terms, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    constexpr int V = decltype(vc)::value;
+    hipLaunchKernelGGL((k_surrogate<M, V>), dim3(a.b), dim3(Plan<M, V>::NT), 0, s, a, terms);
+    return hipGetLastError();
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::revised_waves(int v, const StepArgs& a, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    constexpr int V = decltype(vc)::value, NT = Plan<M, V>::NT;
+    hipLaunchKernelGGL((k_probe_prep<M, V>), dim3(1), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_gather<M, V>), dim3(a.b), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_fft<M, V, false>), dim3(a.b), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_project<M, V>), dim3(a.b), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_fft<M, V, true>), dim3(a.b), dim3(NT), 0, s, a);
+    return hipGetLastError();
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::numerators(int v, int L, const StepArgs& a, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    return with_levels(L, [&](auto lc) {
+      constexpr int V = decltype(vc)::value, LV = decltype(lc)::value;
+      hipLaunchKernelGGL((k_numerators<M, V, LV>), dim3(a.b), dim3(Plan<M, V>::NT), 0, s, a);
+      return hipGetLastError();
+    });
   });
 }
 

@@ -113,9 +113,18 @@ hipError_t launch_normalize_probe(int m, float2* probe, double dp_avg, int* zero
   EMG_BY_M(m, normalize(probe, dp_avg, zero_flag, s));
 }
 hipError_t launch_misfit_terms(int m, int v, const float2* obj, int n, const float2* probe,
-                               const float* dperm, const int2* pos, int n_pos, const float2* tw,
-                               double* phi_all, hipStream_t s) {
-  EMG_BY_M(m, misfit(v, obj, n, probe, dperm, pos, n_pos, tw, phi_all, s));
+                               const float* dperm, const int2* pos, const int4* slot, int count,
+                               const float2* tw, double* phi_out, hipStream_t s) {
+  EMG_BY_M(m, misfit(v, obj, n, probe, dperm, pos, slot, count, tw, phi_out, s));
+}
+hipError_t launch_revised_waves(int m, int v, const StepArgs& a, hipStream_t s) {
+  EMG_BY_M(m, revised_waves(v, a, s));
+}
+hipError_t launch_numerators(int m, int v, int L, const StepArgs& a, hipStream_t s) {
+  EMG_BY_M(m, numerators(v, L, a, s));
+}
+hipError_t launch_surrogate_terms(int m, int v, const StepArgs& a, double* terms, hipStream_t s) {
+  EMG_BY_M(m, surrogate(v, a, terms, s));
 }
 hipError_t launch_grad(int m, int v, bool f64, const GradArgs& g, hipStream_t s) {
   EMG_BY_M(m, grad(v, f64, g, s));

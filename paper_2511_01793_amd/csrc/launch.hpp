@@ -90,10 +90,19 @@ hipError_t launch_layout_intensities(int m, int v, const float* d, float* dperm,
 hipError_t launch_normalize_probe(int m, float2* probe, double dp_avg, int* zero_flag,
                                   hipStream_t s);
 
-// misfit terms of all patterns -> phi_all (N doubles), unreduced
+// misfit terms, unreduced: of all patterns (slot == nullptr; count = N, pattern k at
+// pos[k]) or of the count patterns of a slot list -> phi_out (count doubles)
 hipError_t launch_misfit_terms(int m, int v, const float2* obj, int n, const float2* probe,
-                               const float* dperm, const int2* pos, int n_pos, const float2* tw,
-                               double* phi_all, hipStream_t s);
+                               const float* dperm, const int2* pos, const int4* slot, int count,
+                               const float2* tw, double* phi_out, hipStream_t s);
+
+// Check mode of one minibatch, in three parts on a.slot / a.b:
+//   revised waves R_k of the current state into a.stack and Phi_k into a.phi (the plain
+//   path's first five kernels); numerators from a.stack (its sixth); surrogate terms
+//   1/2 ||Q . z_k - R_k||^2 of the current state against a.stack.
+hipError_t launch_revised_waves(int m, int v, const StepArgs& a, hipStream_t s);
+hipError_t launch_numerators(int m, int v, int L, const StepArgs& a, hipStream_t s);
+hipError_t launch_surrogate_terms(int m, int v, const StepArgs& a, double* terms, hipStream_t s);
 
 // gradient of the misfit (float or double state), chunked over patterns
 struct GradArgs {
@@ -134,8 +143,11 @@ struct Launchers {
                            hipStream_t s);
   static hipError_t normalize(float2* probe, double dp_avg, int* flag, hipStream_t s);
   static hipError_t misfit(int v, const float2* obj, int n, const float2* probe, const float* dperm,
-                           const int2* pos, int n_pos, const float2* tw, double* phi_all,
-                           hipStream_t s);
+                           const int2* pos, const int4* slot, int count, const float2* tw,
+                           double* phi_out, hipStream_t s);
+  static hipError_t revised_waves(int v, const StepArgs& a, hipStream_t s);
+  static hipError_t numerators(int v, int L, const StepArgs& a, hipStream_t s);
+  static hipError_t surrogate(int v, const StepArgs& a, double* terms, hipStream_t s);
   static hipError_t grad(int v, bool f64, const GradArgs& g, hipStream_t s);
 };
 

@@ -32,7 +32,7 @@ EXPORTS = [
     "emagpie_misfit", "emagpie_grad", "emagpie_permutation", "emagpie_last_error",
     "emagpie_version", "emagpie_profile_enable", "emagpie_profile_read",
     "emagpie_group_workspace_size", "emagpie_group_create", "emagpie_group_epoch",
-    "emagpie_group_destroy", "emagpie_plan_get", "emagpie_plan_describe",
+    "emagpie_group_destroy", "emagpie_plan_get", "emagpie_plan_describe", "emagpie_check_step",
 ]
 
 
@@ -108,6 +108,7 @@ def lib() -> ctypes.CDLL:
         "emagpie_group_epoch": [vp, vp, vp, i64, vp, vp],
         "emagpie_group_destroy": [vp],
         "emagpie_plan_get": [vp, ctypes.POINTER(Plan)],
+        "emagpie_check_step": [vp, vp, vp, vp, i32, vp, vp],
         "emagpie_plan_describe": [i32, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
@@ -270,6 +271,16 @@ class Reconstruction:
             _expect(perm, torch.int32, (self.n_pos,), "perm")
         _check(lib().emagpie_epoch(self._ctx, obj.data_ptr(), probe.data_ptr(), int(epoch),
                                    _ptr(perm), _ptr(sampled), _stream()))
+
+    def check_step(self, obj, probe, idx) -> torch.Tensor:
+        """One minibatch update (as step()) that also returns, in float64 on the device,
+        [Phi_B before, surrogate of Eq. 3 after (R frozen before), Phi_B after]."""
+        self._state(obj, probe)
+        t = self._indices(idx)
+        out = torch.empty(3, dtype=torch.float64, device="cuda")
+        _check(lib().emagpie_check_step(self._ctx, obj.data_ptr(), probe.data_ptr(), t.data_ptr(),
+                                        t.numel(), out.data_ptr(), _stream()))
+        return out
 
     def mg_cycle(self, obj, probe, idx) -> torch.Tensor:
         self._state(obj, probe)
