@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/emagpie.h"
+#include "emagpie.h"
 #include "launch.hpp"
 #include "plans.hpp"
 

@@ -37,25 +37,29 @@ template <typename T>
 __device__ __forceinline__ cx<T> add(cx<T> a, cx<T> b) { return cx<T>{a.re + b.re, a.im + b.im}; }
 template <typename T>
 __device__ __forceinline__ cx<T> sub(cx<T> a, cx<T> b) { return cx<T>{a.re - b.re, a.im - b.im}; }
+// Products use explicit fused multiply-adds (one product rounded, then fused
+// into the other).  Floating-point contraction is otherwise off, so each of
+// these rounds the same way in every kernel that inlines it.
 template <typename T>
 __device__ __forceinline__ cx<T> mul(cx<T> a, cx<T> b) {
-  return cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-// complex product with two explicit fused multiply-adds (twiddles); explicit,
-// so it rounds the same way in every kernel that uses it
-template <typename T>
-__device__ __forceinline__ cx<T> mul_fma(cx<T> a, cx<T> b) {
   return cx<T>{fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
 }
+template <typename T>
+__device__ __forceinline__ cx<T> mul_fma(cx<T> a, cx<T> b) { return mul(a, b); }
 // conj(a) * b
 template <typename T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
-  return cx<T>{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+  return cx<T>{fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -(a.im * b.re))};
 }
 template <typename T>
 __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return cx<T>{a.re * s, a.im * s}; }
+// a + s * b
 template <typename T>
-__device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ cx<T> axpy(T s, cx<T> b, cx<T> a) {
+  return cx<T>{fma(s, b.re, a.re), fma(s, b.im, a.im)};
+}
+template <typename T>
+__device__ __forceinline__ T norm2(cx<T> a) { return fma(a.re, a.re, a.im * a.im); }
 template <typename T>
 __device__ __forceinline__ cx<T> conjg(cx<T> a) { return cx<T>{a.re, -a.im}; }
 // multiply by -i (forward) or +i (inverse)
@@ -117,9 +121,11 @@ __device__ __forceinline__ void dft8(cx<T>* v) {
   v[7] = sub(e3, t3);
 }
 
-// 16-point DFT as two 8-point halves; W16^k = W_m^(k m/16) from the table.
-template <typename T, bool INV, int M>
-__device__ __forceinline__ void dft16(cx<T>* v, const cx<T>* tw) {
+// 16-point DFT as two 8-point halves: X_k = E_k + W16^k O_k, X_{k+8} = E_k - W16^k O_k,
+// with W16^k = exp(-+2 pi i k / 16) as constants (W16^4 = -+i, W16^2 and W16^6 through
+// the 1/sqrt(2) form of the 8-point transform, the odd powers through fused products).
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cx<T>* v) {
   cx<T> e[8], o[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -128,13 +134,25 @@ __device__ __forceinline__ void dft16(cx<T>* v, const cx<T>* tw) {
   }
   dft8<T, INV>(e);
   dft8<T, INV>(o);
+  const T c1 = T(0.92387953251128675612818318939678828682);  // cos(pi / 8)
+  const T s1 = T(0.38268343236508977172845998403039886676);  // sin(pi / 8)
+  const T h = T(0.70710678118654752440084436210484903928);
+  const T sg = INV ? T(1) : T(-1);  // sign of the imaginary parts of W16^k, k = 1..7
+  cx<T> t[8];
+  t[0] = o[0];
+  t[1] = mul(cx<T>{c1, sg * s1}, o[1]);
+  t[2] = INV ? cx<T>{h * (o[2].re - o[2].im), h * (o[2].re + o[2].im)}
+             : cx<T>{h * (o[2].re + o[2].im), h * (o[2].im - o[2].re)};
+  t[3] = mul(cx<T>{s1, sg * c1}, o[3]);
+  t[4] = rot90<T, INV>(o[4]);
+  t[5] = mul(cx<T>{-s1, sg * c1}, o[5]);
+  t[6] = INV ? cx<T>{-h * (o[6].re + o[6].im), h * (o[6].re - o[6].im)}
+             : cx<T>{h * (o[6].im - o[6].re), -h * (o[6].re + o[6].im)};
+  t[7] = mul(cx<T>{-c1, sg * s1}, o[7]);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    cx<T> w = tw[k * (M / 16)];
-    if (INV) w = conjg(w);
-    cx<T> t = mul_fma(w, o[k]);
-    v[k] = add(e[k], t);
-    v[k + 8] = sub(e[k], t);
+    v[k] = add(e[k], t[k]);
+    v[k + 8] = sub(e[k], t[k]);
   }
 }
 
@@ -148,7 +166,7 @@ __device__ __forceinline__ void dft_small(cx<T>* v, const cx<T>* tw) {
     dft8<T, INV>(v);
   } else {
     static_assert(R == 16, "radix");
-    dft16<T, INV, M>(v, tw);
+    dft16<T, INV>(v);
   }
 }
 
@@ -212,6 +230,63 @@ __device__ __forceinline__ void fft2_forward(cx<T>* A, const cx<T>* tw, int tid)
   __syncthreads();
   fft_pass<T, M, V, false, false, true>(A, tw, tid);
   __syncthreads();
+}
+
+// The forward transform without its last pass, and the inverse without its
+// first.  The last forward pass and the first inverse pass are the same
+// contiguous column pass (same items per thread, no twiddles), so a caller can
+// run both in registers with per-element work between them (fft_pass_pair).
+template <typename T, int M, int V>
+__device__ __forceinline__ void fft2_forward_head(cx<T>* A, const cx<T>* tw, int tid) {
+  fft_pass<T, M, V, false, true, false>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, V, false, false, false>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, V, false, true, true>(A, tw, tid);
+  __syncthreads();
+}
+template <typename T, int M, int V>
+__device__ __forceinline__ void fft2_inverse_tail(cx<T>* A, const cx<T>* tw, int tid) {
+  fft_pass<T, M, V, true, true, true>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, V, true, false, false>(A, tw, tid);
+  __syncthreads();
+  fft_pass<T, M, V, true, true, false>(A, tw, tid);
+  __syncthreads();
+}
+
+// Items of the contiguous column pass: ITEMS = M * R2 lines of R1 points;
+// item w covers LDS positions (R1 * (w / M) + j) * (M + 1) + w % M, j < R1.
+template <int M, int V>
+struct ColPass {
+  static constexpr int R1 = Plan<M, V>::R1, R2 = Plan<M, V>::R2, NT = Plan<M, V>::NT;
+  static constexpr int ITEMS = M * R2;
+  static constexpr int IT = ITEMS >= NT ? ITEMS / NT : 1;  // items per thread
+  static constexpr int PTS = IT * R1;                        // points per thread
+};
+
+// Last forward pass, f(item point, value) on each transformed value, first
+// inverse pass: in registers, one LDS read and one write per point.  Caller
+// synchronises before (the head's barrier) and after.
+template <typename T, int M, int V, class F>
+__device__ __forceinline__ void fft_pass_pair(cx<T>* A, int tid, F f) {
+  using C = ColPass<M, V>;
+  constexpr int LS = lds_stride<M>();
+#pragma unroll
+  for (int it = 0; it < C::IT; ++it) {
+    const int w = tid + it * C::NT;
+    if (C::ITEMS < C::NT && w >= C::ITEMS) break;
+    const int line = w % M, g = w / M;
+    cx<T> v[C::R1];
+#pragma unroll
+    for (int j = 0; j < C::R1; ++j) v[j] = A[(C::R1 * g + j) * LS + line];
+    dft_small<T, false, C::R1, M>(v, nullptr);
+#pragma unroll
+    for (int j = 0; j < C::R1; ++j) f(it * C::R1 + j, v[j]);
+    dft_small<T, true, C::R1, M>(v, nullptr);
+#pragma unroll
+    for (int j = 0; j < C::R1; ++j) A[(C::R1 * g + j) * LS + line] = v[j];
+  }
 }
 
 // Inverse 2-D DFT without the 1/m^2 factor: transform order in, natural out.

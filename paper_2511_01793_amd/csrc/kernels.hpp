@@ -206,20 +206,25 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, 
     blk_origin<M, V>(tid, rd, r0, c0);
     cx<float> q[4], zz[4], R[4];
     load(rd, r0, c0, q, zz, R);
-    float q2[4], u[4];
+    // per pixel: |Q|^2, u, D = |Q|^2 + u, conj(Q) R (shared by the coarse-grid residual
+    // g = conj(Q)(R - Q z) = conj(Q) R - |Q|^2 z and the object numerator)
+    float q2[4], u[4], D[4];
+    cx<float> cqR[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       q2[e] = norm2(q[e]);
       u[e] = a.alpha * (qqmax - q2[e]);
+      D[e] = q2[e] + u[e];
+      cqR[e] = cmulc(q[e], R[e]);
     }
-    // block sums of g = conj(Q)(R - Q z), D, u, Q, |Q|^2
+    // block sums of g, D, u, Q, |Q|^2
     cx<float> Gs{0.f, 0.f}, Qs{0.f, 0.f};
     float Ds = 0.f, Us = 0.f, Q2s = 0.f;
     if constexpr (L >= 2) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        Gs = add(Gs, cmulc(q[e], sub(R[e], mul(q[e], zz[e]))));
-        Ds += q2[e] + u[e];
+        Gs = add(Gs, axpy(-q2[e], zz[e], cqR[e]));
+        Ds += D[e];
         Us += u[e];
         Qs = add(Qs, q[e]);
         Q2s += q2[e];
@@ -235,22 +240,21 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, 
       const cx<float> G2{quad_sum(w * Gs.re), quad_sum(w * Gs.im)};
       const float D2 = quad_sum(w * Ds);
       const cx<float> c2 = D2 > 0.f ? scale(G2, 1.f / D2) : cx<float>{0.f, 0.f};
-      if (Ds > 0.f) cc = scale(add(Gs, scale(c2, Us)), 1.f / Ds);
+      if (Ds > 0.f) cc = scale(axpy(Us, c2, Gs), 1.f / Ds);
     }
-    // numerators and denominators
+    // numerators N = conj(Q) R + u z', M = conj(z) R + u_z Q and denominators
     cx<float> N[4], Mn[4];
-    float E[4], D[4];
+    float E[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      D[e] = q2[e] + u[e];
       const cx<float> zp = add(zz[e], cc);
-      N[e] = add(cmulc(q[e], R[e]), scale(zp, u[e]));
+      N[e] = axpy(u[e], zp, cqR[e]);
       if (a.zplus) {
         N[e] = D[e] > 0.f ? scale(N[e], 1.f / D[e]) : zp;
       } else {
         const float z2 = norm2(zz[e]);
         const float uz = a.alpha_z * (zmax - z2);
-        Mn[e] = add(cmulc(zz[e], R[e]), scale(q[e], uz));
+        Mn[e] = axpy(uz, q[e], cmulc(zz[e], R[e]));
         E[e] = z2 + uz;
       }
     }
@@ -278,19 +282,26 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, 
 // factor Psi/|Psi| uses the hardware reciprocal square root (within one ulp)
 // instead of a correctly rounded square root and division.  |Psi|^2 below the
 // smallest normal float (|Psi| < 1.1e-19) counts as zero: theta := 0 there.
+// Written with selects only, so no lane branches.
 template <int M>
 __device__ __forceinline__ float project_amp(cx<float>& P, float amp) {
   constexpr float kTiny = 1.17549435e-38f;  // FLT_MIN
+  constexpr float kInvM2 = 1.f / float(M * M);
   const float p2 = norm2(P);
   const bool live = p2 >= kTiny;
-  const float ir = __builtin_amdgcn_rsqf(live ? p2 : 1.f);
-  const float diff = live ? p2 * ir - amp : -amp;
-  P = live ? scale(P, amp * ir * (1.f / float(M * M))) : cx<float>{amp * (1.f / float(M * M)), 0.f};
+  const float ir = __builtin_amdgcn_rsqf(fmaxf(p2, kTiny));
+  const float diff = (live ? p2 * ir : 0.f) - amp;
+  const float f = amp * ir * kInvM2;
+  P.re = live ? P.re * f : amp * kInvM2;
+  P.im = live ? P.im * f : 0.f;
   return diff * diff;
 }
+// measured amplitude a = sqrt(max(d, 0)) of one intensity (hardware square root,
+// within one ulp)
+__device__ __forceinline__ float amplitude(float d) { return __builtin_amdgcn_sqrtf(fmaxf(d, 0.f)); }
 template <int M>
 __device__ __forceinline__ float project_px(cx<float>& P, float dval) {
-  return project_amp<M>(P, sqrtf(fmaxf(dval, 0.f)));
+  return project_amp<M>(P, amplitude(dval));
 }
 
 // ---------------------------------------------------------------------------
@@ -308,24 +319,21 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
   const float2* zwin = a.obj + (size_t)sl.y * n + sl.z;
   const float* dk = a.dperm + (size_t)k * M * M;
   // every global load of the patch is issued here, before any dependent work:
-  // probe rows as 16-byte pairs, amplitude rows as 8-byte pairs, the object
-  // window (arbitrary alignment) per pixel
+  // amplitudes in the order the projection visits them (contiguous across
+  // lanes), probe rows as 16-byte pairs, the object window (arbitrary
+  // alignment) per pixel
+  using CP = ColPass<M, V>;
   cx<float> qc[P::CACHE ? 4 : 1], zc[P::CACHE ? 4 : 1];
-  float amp[4 * R];
+  float amp[CP::PTS];
   float q2m = 0.f, z2m = 0.f;
 #pragma unroll
-  for (int rd = 0; rd < R; ++rd) {
-    int r0, c0;
-    blk_origin<M, V>(tid, rd, r0, c0);
+  for (int it = 0; it < CP::IT; ++it) {
+    const int w = tid + it * CP::NT;
+    if (CP::ITEMS < CP::NT && w >= CP::ITEMS) break;
+    const int line = w % M, g = w / M;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const float2 dv = *reinterpret_cast<const float2*>(dk + (r0 + i) * M + c0);
-      amp[4 * rd + 2 * i] = dv.x;
-      amp[4 * rd + 2 * i + 1] = dv.y;
-    }
+    for (int j = 0; j < CP::R1; ++j) amp[it * CP::R1 + j] = dk[(CP::R1 * g + j) * M + line];
   }
-#pragma unroll
-  for (int e = 0; e < 4 * R; ++e) amp[e] = sqrtf(fmaxf(amp[e], 0.f));
 #pragma unroll
   for (int rd = 0; rd < R; ++rd) {
     int r0, c0;
@@ -352,20 +360,16 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
   // before they are read in the per-pixel phase
   wave_max2_to_lds<NT>(q2m, z2m, redf, tid);
   __syncthreads();
-  fft2_forward<float, M, V>(A, tws, tid);
+  fft2_forward_head<float, M, V>(A, tws, tid);
+  // last forward pass, modulus projection, first inverse pass, in registers
   double acc = 0.0;
-#pragma unroll
-  for (int rd = 0; rd < R; ++rd) {
-    int r0, c0;
-    blk_origin<M, V>(tid, rd, r0, c0);
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      acc += (double)project_amp<M>(A[(r0 + (e >> 1)) * LS + c0 + (e & 1)], amp[4 * rd + e]);
-  }
+  fft_pass_pair<float, M, V>(A, tid, [&](int e, cx<float>& v) {
+    acc += (double)project_amp<M>(v, amplitude(amp[e]));
+  });
   acc = wave_sum(acc);
   if ((tid & 63) == 0) redd[tid >> 6] = acc;
   __syncthreads();
-  fft2_inverse<float, M, V>(A, tws, tid);
+  fft2_inverse_tail<float, M, V>(A, tws, tid);
   float qqmax, zmax;
   lds_max2<NT>(redf, qqmax, zmax);
   pixel_update<M, V, L>(
