@@ -189,6 +189,7 @@ emg::StepArgs base_args(emagpie_ctx c, void* obj, void* probe) {
   a.alpha_z = c->cfg.alpha_z;
   a.update_probe = c->cfg.update_probe;
   a.joint = c->cfg.joint_step;
+  a.pgroups = emg::probe_groups(c->cfg.minibatch);
   a.tw = c->tw32;
   a.numer = c->numer;
   a.pnum = c->pnum;
@@ -980,7 +981,8 @@ emagpie_status plan_group(int32_t n_inst, const emagpie_ctx* ctxs, GroupLayout* 
         const emagpie_config& c = ctxs[i]->cfg;
         if (j * c.minibatch >= c.n_pos) continue;
         int items = 0;
-        if (emg::finalize_item_count(c.m, c.finalize_shape, c.n, &items) != hipSuccess)
+        if (emg::finalize_item_count(c.m, c.finalize_shape, c.n, emg::probe_groups(c.minibatch),
+                                     &items) != hipSuccess)
           return fail(EMAGPIE_E_SHAPE, "unsupported probe size in group");
         for (int t = 0; t < items; ++t) G->work_host.push_back(make_int2(j * n_inst + i, t));
       }

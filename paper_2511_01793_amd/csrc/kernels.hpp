@@ -144,6 +144,7 @@ __device__ __forceinline__ void st_pair(float2* p, size_t i, cx<float> a, cx<flo
   *reinterpret_cast<float4*>(p + i) = make_float4(a.re, a.im, b.re, b.im);
 }
 
+
 template <int M, int V>
 struct Px {
   static constexpr int NT = Plan<M, V>::NT, LS = lds_stride<M>();
@@ -400,14 +401,13 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
 // finalize: FNT threads per work item
 //   object tile (item < ntiles): T x T pixels, accumulate the numerators of the
 //   overlapping slots in ascending slot order, divide, joint step;
-//   probe units: 64 pixels x 4 slot groups per 256 threads, groups combined in
-//   a fixed order, then the joint step.
+//   probe units: FNT / G pixels x G slot groups (G from the minibatch size),
+//   groups combined in a fixed order, then the joint step.
 // ---------------------------------------------------------------------------
 template <int FNT, int T_>
 struct Fin {
   static constexpr int T = T_;
   static constexpr int PER = T * T / FNT;
-  static constexpr int PROBE_PX = FNT / 4;  // probe pixels per item
   static_assert(PER * FNT == T * T && FNT % 256 == 0, "finalize shape");
 };
 // the finalize shape used inside the persistent kernel (FNT = the plan's NT)
@@ -424,11 +424,13 @@ struct FinLds {
   float pe[1024];
 };
 
+// object tiles, then probe units of FNT / G pixels (G slot groups per pixel)
 template <int M, int FNT, int T>
-__host__ __device__ inline int finalize_items(int n, int* ntiles_out) {
+__host__ __device__ inline int finalize_items(int n, int G, int* ntiles_out) {
   const int tpr = (n + T - 1) / T;
+  const int ppu = FNT / G;
   *ntiles_out = tpr * tpr;
-  return tpr * tpr + (M * M + Fin<FNT, T>::PROBE_PX - 1) / Fin<FNT, T>::PROBE_PX;
+  return tpr * tpr + (M * M + ppu - 1) / ppu;
 }
 
 template <int M, int FNT>
@@ -444,6 +446,15 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
   if (item < ntiles) {
     const int tpr = (n + T - 1) / T;
     const int ty = (item / tpr) * T, tx = (item % tpr) * T;
+    // the current object values are needed by the joint step at the end: their
+    // loads go out first, beside the slot scan
+    cx<float> zold[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int q = tid + e * FNT;
+      const int y = ty + q / T, x = tx + q % T;
+      zold[e] = (a.joint && y < n && x < n) ? ld(a.obj, (size_t)y * n + x) : cx<float>{0.f, 0.f};
+    }
     // wave 0 lists the overlapping slots in ascending order
     if (tid < 64) {
       int cnt = 0;
@@ -508,23 +519,26 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
         if (accd[e] > 0.f && y < n && x < n) {
           const size_t o = (size_t)y * n + x;
           const cx<float> zp = scale(accn[e], 1.f / accd[e]);
-          st(a.obj, o, a.joint ? aligned_sqrt(ld(a.obj, o), zp) : zp);
+          st(a.obj, o, a.joint ? aligned_sqrt(zold[e], zp) : zp);
         }
       }
     }
     __syncthreads();  // the slot list is rewritten by the next tile
   } else {
-    const int lt = tid & 255, unit = tid >> 8;
-    const int g = lt >> 6;
-    const int r = (item - ntiles) * Fin<FNT, T>::PROBE_PX + unit * 64 + (lt & 63);
+    // probe unit: ppu pixels x G slot groups; group g sums slots [g per, (g + 1) per)
+    // in ascending order, then the G partials are added in group order
+    const int G = a.pgroups, ppu = FNT / G;
+    const int g = tid / ppu, lp = tid - g * ppu;
+    const int r = (item - ntiles) * ppu + lp;
     const bool live = a.update_probe && r < M * M;
-    const int per = (a.b + 3) / 4;
-    const int s_lo = g * per, s_hi = min(a.b, s_lo + per);
+    const cx<float> qold = (live && g == 0 && a.joint) ? ld(a.probe, r) : cx<float>{0.f, 0.f};
+    const int per = (a.b + G - 1) / G;
+    const int s_lo = min(a.b, g * per), s_hi = min(a.b, s_lo + per);
     cx<float> mac{0.f, 0.f};
     float eac = 0.f;
     if (live) {
       // U slots per round: the round's loads are all issued before its adds
-      constexpr int U = FNT >= 1024 ? 4 : 8;
+      constexpr int U = 8;
       for (int s0 = s_lo; s0 < s_hi; s0 += U) {
         cx<float> vm[U];
         float ve[U];
@@ -549,15 +563,15 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
     L.pe[tid] = eac;
     __syncthreads();
     if (g == 0 && live) {
-      const int b0 = unit * 256 + (lt & 63);
-      const cx<float> m01 = add(ld(L.pm, b0), ld(L.pm, b0 + 64));
-      const cx<float> m23 = add(ld(L.pm, b0 + 128), ld(L.pm, b0 + 192));
-      const float e01 = L.pe[b0] + L.pe[b0 + 64], e23 = L.pe[b0 + 128] + L.pe[b0 + 192];
-      const cx<float> mt = add(m01, m23);
-      const float et = e01 + e23;
+      cx<float> mt = ld(L.pm, lp);
+      float et = L.pe[lp];
+      for (int k = 1; k < G; ++k) {
+        mt = add(mt, ld(L.pm, lp + k * ppu));
+        et += L.pe[lp + k * ppu];
+      }
       if (et > 0.f) {
         const cx<float> qp = scale(mt, 1.f / et);
-        st(a.probe, r, a.joint ? aligned_sqrt(ld(a.probe, r), qp) : qp);
+        st(a.probe, r, a.joint ? aligned_sqrt(qold, qp) : qp);
       }
     }
     if (item == ntiles && tid == 0 && a.sampled) {
@@ -629,7 +643,7 @@ __global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize_multi(const StepA
   const int2 w = work[blockIdx.x];
   const StepArgs a = args[w.x];
   int ntiles;
-  finalize_items<M, FNT, T>(a.n, &ntiles);
+  finalize_items<M, FNT, T>(a.n, a.pgroups, &ntiles);
   load_slot_positions<M, FNT>(a, L, tid);
   __syncthreads();
   finalize_item<M, FNT, T>(a, w.y, ntiles, L, tid);
@@ -1061,7 +1075,7 @@ hipError_t Launchers<M>::finalize(int f, const StepArgs& a, hipStream_t s, hipEv
   return with_fin(f, [&](auto fc) {
     constexpr int F = decltype(fc)::value, FNT = FinShape<F>::FNT, T = FinShape<F>::T;
     int ntiles;
-    const int items = finalize_items<M, FNT, T>(a.n, &ntiles);
+    const int items = finalize_items<M, FNT, T>(a.n, a.pgroups, &ntiles);
     if (e0) {
       StepArgs aa = a;
       void* args[] = {&aa, &ntiles};
@@ -1098,11 +1112,11 @@ hipError_t Launchers<M>::finalize_multi(int f, const StepArgs* args, const int2*
 }
 
 template <int M>
-hipError_t Launchers<M>::finalize_item_count(int f, int n, int* items) {
+hipError_t Launchers<M>::finalize_item_count(int f, int n, int pgroups, int* items) {
   return with_fin(f, [&](auto fc) {
     constexpr int F = decltype(fc)::value;
     int ntiles = 0;
-    *items = finalize_items<M, FinShape<F>::FNT, FinShape<F>::T>(n, &ntiles);
+    *items = finalize_items<M, FinShape<F>::FNT, FinShape<F>::T>(n, pgroups, &ntiles);
     return hipSuccess;
   });
 }
@@ -1146,7 +1160,7 @@ hipError_t Launchers<M>::persistent_epoch(int v, int L, const StepArgs& a, int n
     return with_levels(L, [&](auto lc) {
       constexpr int V = decltype(vc)::value, LV = decltype(lc)::value, NT = Plan<M, V>::NT;
       int ntiles;
-      int nitems = finalize_items<M, NT, PersistFin<NT>::T>(a.n, &ntiles);
+      int nitems = finalize_items<M, NT, PersistFin<NT>::T>(a.n, a.pgroups, &ntiles);
       StepArgs aa = a;
       int np = n_pos, bb = B;
       unsigned* br = bar;

@@ -90,8 +90,8 @@ hipError_t launch_finalize_multi(int m, int f, const StepArgs* args, const int2*
                                  hipStream_t s) {
   EMG_BY_M(m, finalize_multi(f, args, work, blocks, s));
 }
-hipError_t finalize_item_count(int m, int f, int n, int* items) {
-  EMG_BY_M(m, finalize_item_count(f, n, items));
+hipError_t finalize_item_count(int m, int f, int n, int pgroups, int* items) {
+  EMG_BY_M(m, finalize_item_count(f, n, pgroups, items));
 }
 hipError_t launch_plain_step(int m, int v, int L, const StepArgs& a, hipStream_t s) {
   EMG_BY_M(m, plain_step(v, L, a, s));

@@ -21,6 +21,7 @@ struct StepArgs {
   float alpha, alpha_z;
   int update_probe;
   int joint;         // 1: Eq. 6 joint step; 0: z <- z+, Q <- Q+ (Eq. 2)
+  int pgroups;       // slot groups of the probe sums (probe_groups(minibatch))
   const float2* tw;  // m twiddles exp(-2 pi i j / m)
   // per-slot products of the patch stage
   float2* numer;     // b x m^2 object numerators conj(Q) R + u z'
@@ -53,7 +54,7 @@ hipError_t launch_patch_step_multi(int m, int v, int L, const StepArgs* args, co
 hipError_t launch_finalize_multi(int m, int f, const StepArgs* args, const int2* work, int blocks,
                                  hipStream_t s);
 // number of finalize work items (object tiles + probe units) for an n x n object
-hipError_t finalize_item_count(int m, int f, int n, int* items);
+hipError_t finalize_item_count(int m, int f, int n, int pgroups, int* items);
 
 // plain path: the six patch-stage kernels (finalize is launched separately)
 hipError_t launch_plain_step(int m, int v, int L, const StepArgs& a, hipStream_t s);
@@ -133,7 +134,7 @@ struct Launchers {
                                      int blocks, hipStream_t s);
   static hipError_t finalize_multi(int f, const StepArgs* args, const int2* work, int blocks,
                                    hipStream_t s);
-  static hipError_t finalize_item_count(int f, int n, int* items);
+  static hipError_t finalize_item_count(int f, int n, int pgroups, int* items);
   static hipError_t plain_step(int v, int L, const StepArgs& a, hipStream_t s);
   static hipError_t persistent_grid_size(int v, int L, int num_cus, int* grid);
   static hipError_t persistent_epoch(int v, int L, const StepArgs& a, int n_pos, int B, int grid,

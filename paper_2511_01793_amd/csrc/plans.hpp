@@ -70,4 +70,10 @@ inline bool fin_shape_desc(int f, int* fnt, int* tile) {
   return true;
 }
 
+// Slot groups of the probe sums in the finalize: each probe pixel's sum over
+// the minibatch is split into G contiguous slot ranges added in parallel, then
+// combined in group order.  G depends only on the configured minibatch size,
+// so every path and finalize shape sums in the same order.
+inline int probe_groups(int minibatch) { return minibatch >= 64 ? 16 : (minibatch >= 16 ? 8 : 4); }
+
 }  // namespace emg
