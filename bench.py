@@ -223,6 +223,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-target", action="store_true")
+    ap.add_argument("--plan", type=str, default=None, metavar="V,F,PATH",
+                    help="fix the FFT plan, finalize shape and path of the tuned leg instead of "
+                         "autotuning (e.g. 3,1,fused; for profiler runs, whose timing distorts "
+                         "the autotuner)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
                     help="c2 (default, the headline workload) or c3 (1024^2 object, 128^2 probe, "
                          "10000-point Fermat spiral, minibatch 256, 3 levels)")
@@ -265,7 +269,11 @@ def main():
         rec.close()
     # the autotuner's choice of FFT plan, finalize shape and path (timed at init)
     t0 = time.perf_counter()
-    rec, obj, probe = fresh("auto", E.TUNE, E.TUNE)
+    if args.plan:
+        fv, ff, fp = args.plan.split(",")
+        rec, obj, probe = fresh(fp, int(fv), int(ff))
+    else:
+        rec, obj, probe = fresh("auto", E.TUNE, E.TUNE)
     tune_s = time.perf_counter() - t0
     plan = rec.plan
     t = time_epochs(rec, obj, probe, K, W)
