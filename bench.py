@@ -152,7 +152,8 @@ def cpu_baseline(p, budget_s=10.0):
 
 def bench_group(K, W):
     """16 uneven independent reconstructions: one group epoch (all instances, batched
-    launches, one captured graph) against the same instances swept one after another."""
+    launches, one captured graph) against the same instances swept one after another
+    (each with its autotuned plan and path)."""
     import torch
     import paper_2511_01793_amd.emagpie as E
     from paper_2511_01793_amd import synth
@@ -160,12 +161,14 @@ def bench_group(K, W):
     ps = synth.make_c5()
     total = sum(p.n_pos for p in ps)
 
-    def members(path):
+    def members(path, tune):
         recs, objs, probes = [], [], []
         for i, p in enumerate(ps):
             d = torch.from_numpy(p.intensities).cuda()
             rec = E.Reconstruction(p.positions, d, p.n, minibatch=p.minibatch, levels=p.levels,
-                                   alpha=p.alpha, alpha_z=p.alpha_z, path=path, seed=p.seed)
+                                   alpha=p.alpha, alpha_z=p.alpha_z, path=path, seed=p.seed,
+                                   fft_plan=E.TUNE if tune else 0,
+                                   finalize_shape=E.TUNE if tune else 0)
             obj = torch.from_numpy(p.object_init).cuda()
             probe = torch.from_numpy(p.probe_init).cuda()
             rec.normalize_probe(probe)
@@ -175,7 +178,8 @@ def bench_group(K, W):
             del d
         return recs, objs, probes
 
-    recs, objs, probes = members("graph")
+    # one by one: every member with the plan and path its own autotuning picks
+    recs, objs, probes = members("auto", True)
     for e in range(W):
         for r, o, q in zip(recs, objs, probes):
             r.epoch(o, q, e)
@@ -186,7 +190,11 @@ def bench_group(K, W):
             r.epoch(o, q, W + e)
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t0) / K
-    log(f"one by one (graph each): {t_seq * 1e3:.3f} ms per sweep of all 16, {total / t_seq:.0f} patterns/s")
+    log(f"one by one (autotuned each): {t_seq * 1e3:.3f} ms per sweep of all 16, {total / t_seq:.0f} patterns/s")
+    for r in recs:
+        r.close()
+    # the group: one default plan for all members, so each probe-size class is one branch
+    recs, objs, probes = members("graph", False)
     grp = E.Group(recs)
     for e in range(W):
         grp.epoch(objs, probes, e)
