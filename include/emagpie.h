@@ -56,7 +56,11 @@ enum {
   EMAGPIE_PATH_FUSED = 1,  /* fused per-patch kernel + finalize kernel         */
   EMAGPIE_PATH_GRAPH = 2,  /* FUSED launches replayed from a captured hipGraph */
   EMAGPIE_PATH_PERSISTENT = 3, /* one cooperative launch per epoch, grid barriers */
-  EMAGPIE_PATH_AUTO = 4  /* chosen at init by timing FUSED, GRAPH and PERSISTENT epochs */
+  EMAGPIE_PATH_AUTO = 4, /* chosen at init by timing FUSED, GRAPH and PERSISTENT epochs
+                            (and CHAIN when minibatch = 1)                           */
+  EMAGPIE_PATH_CHAIN = 5 /* minibatch 1 only: one workgroup runs the whole sequential
+                            sweep, each step applied in place (the paper's literal order,
+                            Sec. 3 footnote: positions updated one after another)     */
 };
 
 /* fft_plan / finalize_shape value asking emagpie_init to choose by timing */
@@ -84,6 +88,10 @@ typedef struct {
   int32_t finalize_shape; /* finalize work-item shape 0..3 (0 default), or EMAGPIE_TUNE */
   const char* tune_cache; /* NULL, or a file of autotuning results (JSON lines) that
                            emagpie_init reads before timing and appends to after  */
+  int32_t zero_phase_memory; /* 1: the stateful zero-bin phase rule stated after Eq. 3
+                           (a bin where F(Q z_k) = 0 takes the phase pattern k had at its
+                           previous visit, 0 at the first); the workspace then holds N m^2
+                           unit phasors.  0: theta(0) = 0 always (footnote of Def. 2.1). */
 } emagpie_config;
 
 /*
@@ -103,7 +111,7 @@ typedef struct {
   float fft_us[4];       /* median patch-stage kernel time per candidate, us        */
   int32_t n_fin_shapes;  /* candidates timed (0 if the shape was not timed)         */
   float fin_us[4];       /* median finalize kernel time per candidate, us           */
-  float path_ms[4];      /* median epoch time per path (index EMAGPIE_PATH_*), ms; -1
+  float path_ms[8];      /* median epoch time per path (index EMAGPIE_PATH_*), ms; -1
                             where not timed (PLAIN is never a candidate)            */
 } emagpie_plan;
 
@@ -265,6 +273,13 @@ emagpie_status emagpie_group_create(emagpie_group* out, int32_t n_inst, const em
 emagpie_status emagpie_group_epoch(emagpie_group g, void* const* obj_devs, void* const* probe_devs,
                                    int64_t epoch, double* sampled_misfit_dev, void* stream);
 emagpie_status emagpie_group_destroy(emagpie_group g);
+
+/*
+ * Zero-bin phase memory (zero_phase_memory = 1): set every stored phase back to
+ * 0, i.e. the state of a run's first sweep.  EMAGPIE_E_ARG if the context has no
+ * phase memory.  Stream-ordered.
+ */
+emagpie_status emagpie_phase_memory_reset(emagpie_ctx ctx, void* stream);
 
 /*
  * The plan a context runs with (after any autotuning at init).  Host only.

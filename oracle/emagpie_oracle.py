@@ -79,9 +79,24 @@ def amplitudes(d: np.ndarray) -> np.ndarray:
     return np.sqrt(np.maximum(d, 0.0))
 
 
-def revised_exit_wave(Q: np.ndarray, zk: np.ndarray, ak: np.ndarray) -> np.ndarray:
-    """R_k(Q, z_k) = F^-1( sqrt(d_k) . exp(i theta(F(Q . z_k))) ) (Def. 2.1)."""
-    return idft2(ak * unit_phase(dft2(Q * zk)))
+def revised_exit_wave(Q: np.ndarray, zk: np.ndarray, ak: np.ndarray,
+                      prev_phase: np.ndarray | None = None) -> np.ndarray:
+    """R_k(Q, z_k) = F^-1( sqrt(d_k) . exp(i theta(F(Q . z_k))) ) (Def. 2.1).
+
+    prev_phase (optional, m x m unit phasors exp(i theta)): the stateful rule stated after
+    Eq. 3 -- where F(Q . z_k) is zero, theta is the phase pattern k had at the previous
+    iterate (0 at the first).  Without it theta(0) = 0 (footnote of Def. 2.1).
+    """
+    return idft2(ak * phase_used(dft2(Q * zk), prev_phase))
+
+
+def phase_used(Psi: np.ndarray, prev_phase: np.ndarray | None) -> np.ndarray:
+    """exp(i theta) of Psi, with the zero bins taking prev_phase (or 1 when it is None)."""
+    u = unit_phase(Psi)
+    if prev_phase is not None:
+        zero = np.abs(Psi) == 0
+        u[zero] = prev_phase[zero]
+    return u
 
 
 def misfit_terms(Q, z, positions, a) -> np.ndarray:
@@ -257,7 +272,8 @@ def aligned_sqrt(x: np.ndarray, xplus: np.ndarray) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 def step_minibatch(Q, z, positions, a, idx, *, alpha: float, alpha_z: float = 1.0,
-                   levels: int = 1, update_probe: bool = True, joint: bool = True):
+                   levels: int = 1, update_probe: bool = True, joint: bool = True,
+                   phase_mem: np.ndarray | None = None):
     """Apply one eMAGPIE minibatch update to (Q, z) and return the new state.
 
     For the members k of idx, all evaluated at the state at the start of the batch:
@@ -269,7 +285,9 @@ def step_minibatch(Q, z, positions, a, idx, *, alpha: float, alpha_z: float = 1.
               = sum_k (conj(z_k) R_k + u_z,k Q) / sum_k (|z_k|^2 + u_z,k)   (Eq. 8),
       joint:  z <- aligned_sqrt(z, z^+), Q <- aligned_sqrt(Q, Q^+)  (Eq. 6).
     With one member and one level this is the step of Prop. 3.2 (Eqs. 6-9); joint=False gives
-    the rPIE update of Eq. 2.  Returns (Q_new, z_new, info) with info holding z^+, Q^+, the
+    the rPIE update of Eq. 2.  phase_mem (optional, N x m x m unit phasors, updated in place):
+    the stateful zero-bin phase rule stated after Eq. 3; each member reads its previous phases
+    and stores the ones it used.  Returns (Q_new, z_new, info) with info holding z^+, Q^+, the
     touched mask, the revised waves and the sampled misfit sum_k Phi_k.
     """
     Q = np.asarray(Q, np.complex128)
@@ -287,7 +305,12 @@ def step_minibatch(Q, z, positions, a, idx, *, alpha: float, alpha_z: float = 1.
         p = positions[k]
         r0, c0 = int(p[0]), int(p[1])
         zk = patch(z, p, m).copy()
-        Rk = revised_exit_wave(Q, zk, a[k])
+        if phase_mem is None:
+            Rk = revised_exit_wave(Q, zk, a[k])
+        else:
+            ph = phase_used(dft2(Q * zk), phase_mem[k])
+            Rk = idft2(a[k] * ph)
+            phase_mem[k] = ph
         Rs.append(Rk)
         e = Q * zk - Rk
         phi += 0.5 * float(np.vdot(e, e).real)
@@ -348,7 +371,8 @@ def permutation(seed: int, epoch: int, n: int) -> np.ndarray:
 
 def run_epoch(Q, z, positions, a, *, seed: int, epoch: int, minibatch: int, alpha: float,
               alpha_z: float = 1.0, levels: int = 1, update_probe: bool = True,
-              perm: np.ndarray | None = None, joint: bool = True):
+              perm: np.ndarray | None = None, joint: bool = True,
+              phase_mem: np.ndarray | None = None):
     """One sweep (iteration j) over all scan positions in random order, in consecutive
     minibatches; the last one may be short (Sec. 3, stochastic strategy).  Returns (Q, z, sampled)."""
     n_pos = len(positions)
@@ -357,7 +381,7 @@ def run_epoch(Q, z, positions, a, *, seed: int, epoch: int, minibatch: int, alph
     for s in range(0, n_pos, minibatch):
         Q, z, info = step_minibatch(Q, z, positions, a, order[s:s + minibatch], alpha=alpha,
                                     alpha_z=alpha_z, levels=levels, update_probe=update_probe,
-                                    joint=joint)
+                                    joint=joint, phase_mem=phase_mem)
         sampled += info["sampled_misfit"]
     return Q, z, sampled
 

@@ -65,7 +65,7 @@ bool wants_tuning(const emagpie_config& c) {
 
 struct Layout {
   Region dperm, pos, slots, tw32, tw64, numer, pnum, pden, pden_slot, phi, stack, zmax, ubuf, Dbuf, scal,
-      bar, phi_all, gz, gq, tune_obj, tune_probe;
+      bar, phi_all, gz, gq, tune_obj, tune_probe, phase;
   int grad_chunk;
   size_t total;
 };
@@ -106,6 +106,7 @@ Layout make_layout(const emagpie_config& c) {
   const bool tune = wants_tuning(c);
   L.tune_obj = take(tune ? (size_t)c.n * c.n * 8 : 0);
   L.tune_probe = take(tune ? m2 * 8 : 0);
+  L.phase = take(c.zero_phase_memory ? N * m2 * 8 : 0);
   L.total = cur;
   return L;
 }
@@ -124,8 +125,12 @@ emagpie_status check_config(const emagpie_config* c) {
     return fail(EMAGPIE_E_ARG, "alpha_z must be finite and >= 0");
   if (c->update_probe != 0 && c->update_probe != 1) return fail(EMAGPIE_E_ARG, "update_probe must be 0 or 1");
   if (c->joint_step != 0 && c->joint_step != 1) return fail(EMAGPIE_E_ARG, "joint_step must be 0 or 1");
-  if (c->path < EMAGPIE_PATH_PLAIN || c->path > EMAGPIE_PATH_AUTO)
+  if (c->path < EMAGPIE_PATH_PLAIN || c->path > EMAGPIE_PATH_CHAIN)
     return fail(EMAGPIE_E_ARG, "unknown path");
+  if (c->path == EMAGPIE_PATH_CHAIN && c->minibatch != 1)
+    return fail(EMAGPIE_E_ARG, "the chain path needs minibatch 1");
+  if (c->zero_phase_memory != 0 && c->zero_phase_memory != 1)
+    return fail(EMAGPIE_E_ARG, "zero_phase_memory must be 0 or 1");
   if (c->fft_plan != EMAGPIE_TUNE && (c->fft_plan < 0 || c->fft_plan >= emg::fft_plan_count(c->m)))
     return fail(EMAGPIE_E_ARG, "fft_plan must be EMAGPIE_TUNE or in [0, " +
                                    std::to_string(emg::fft_plan_count(c->m)) + ") for this m");
@@ -153,6 +158,7 @@ struct emagpie_ctx_s {
   double* scal_d;  // [0] dp sum, [1] scratch
   int* scal_i;     // [0] bad-data flag, [1] zero-probe flag
   float* qqmax;
+  float2* phase = nullptr;  // zero-bin phase memory (N x m^2 unit phasors) or null
   std::vector<int32_t> pos_host;
   std::vector<int32_t> perm_host;
   double dp_avg = 0.0;
@@ -190,6 +196,8 @@ emg::StepArgs base_args(emagpie_ctx c, void* obj, void* probe) {
   a.update_probe = c->cfg.update_probe;
   a.joint = c->cfg.joint_step;
   a.pgroups = emg::probe_groups(c->cfg.minibatch);
+  a.phase = c->phase;
+  a.phase_write = 1;
   a.tw = c->tw32;
   a.numer = c->numer;
   a.pnum = c->pnum;
@@ -280,7 +288,8 @@ void fill_plan_info(emagpie_ctx c, int tuned) {
   p.tuned = tuned;
   if (tuned == 0) {
     p.n_fft_plans = p.n_fin_shapes = 0;
-    for (int i = 0; i < 4; ++i) p.fft_us[i] = p.fin_us[i] = p.path_ms[i] = -1.f;
+    for (int i = 0; i < 4; ++i) p.fft_us[i] = p.fin_us[i] = -1.f;
+    for (float& x : p.path_ms) x = -1.f;
   }
 }
 
@@ -295,9 +304,11 @@ std::string tune_key(emagpie_ctx c, const emagpie_config& req) {
   const emagpie_config& k = c->cfg;
   char buf[512];
   std::snprintf(buf, sizeof buf,
-                "%s cus=%d m=%d n=%d N=%d B=%d L=%d blind=%d joint=%d az1=%d plan=%d shape=%d path=%d",
+                "%s cus=%d m=%d n=%d N=%d B=%d L=%d blind=%d joint=%d az1=%d mem=%d plan=%d shape=%d "
+                "path=%d",
                 arch.c_str(), c->num_cus, k.m, k.n, k.n_pos, k.minibatch, k.levels, k.update_probe,
-                k.joint_step, k.alpha_z == 1.0f ? 1 : 0, req.fft_plan, req.finalize_shape, req.path);
+                k.joint_step, k.alpha_z == 1.0f ? 1 : 0, k.zero_phase_memory, req.fft_plan,
+                req.finalize_shape, req.path);
   return buf;
 }
 
@@ -353,7 +364,7 @@ void cache_append(const char* path, const std::string& key, const emagpie_plan& 
                "{\"key\": \"%s\", \"fft_plan\": %d, \"finalize_shape\": %d, \"path\": %d, "
                "\"fft_us\": %s, \"fin_us\": %s, \"path_ms\": %s}\n",
                key.c_str(), p.fft_plan, p.finalize_shape, p.path, arr(p.fft_us, 4).c_str(),
-               arr(p.fin_us, 4).c_str(), arr(p.path_ms, 4).c_str());
+               arr(p.fin_us, 4).c_str(), arr(p.path_ms, 6).c_str());
   std::fclose(fp);
 }
 
@@ -407,7 +418,8 @@ emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* i
   const std::string key = tune_key(c, req);
   int cv, cf, cp;
   if (cache_lookup(req.tune_cache, key, &cv, &cf, &cp) && cv >= 0 && cv < emg::fft_plan_count(m) &&
-      cf >= 0 && cf < emg::kFinShapes && cp >= EMAGPIE_PATH_PLAIN && cp <= EMAGPIE_PATH_PERSISTENT) {
+      cf >= 0 && cf < emg::kFinShapes && cp >= EMAGPIE_PATH_PLAIN && cp <= EMAGPIE_PATH_CHAIN &&
+      cp != EMAGPIE_PATH_AUTO && (cp != EMAGPIE_PATH_CHAIN || B == 1)) {
     EMG_OK(relayout(c, cv, intensities_dev, s));
     c->cfg.fft_plan = cv;
     c->cfg.finalize_shape = cf;
@@ -479,9 +491,11 @@ emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* i
   }
   // 3. path: whole epochs on the scratch state
   if (req.path == EMAGPIE_PATH_AUTO) {
-    const int cand[3] = {EMAGPIE_PATH_FUSED, EMAGPIE_PATH_GRAPH, EMAGPIE_PATH_PERSISTENT};
+    const int cand[4] = {EMAGPIE_PATH_FUSED, EMAGPIE_PATH_GRAPH, EMAGPIE_PATH_PERSISTENT,
+                         EMAGPIE_PATH_CHAIN};
     int best = EMAGPIE_PATH_FUSED;
     for (int p : cand) {
+      if (p == EMAGPIE_PATH_CHAIN && B != 1) continue;
       c->cfg.path = p;
       float ms = -1.f;
       int64_t epoch = 0;
@@ -497,6 +511,9 @@ emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* i
     c->cfg.path = best;
     drop_graph(c);
   }
+  // the timed runs wrote phasors of the scratch state: back to the first-sweep state
+  if (c->phase)
+    EMG_HIP(emg::launch_fill_c64(c->phase, (size_t)N * m * m, make_float2(1.f, 0.f), s));
   EMG_HIP(hipStreamSynchronize(s));
   fill_plan_info(c, 1);
   cache_append(req.tune_cache, key, P);
@@ -573,6 +590,7 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   ctx->qqmax = reinterpret_cast<float*>(w + lay.scal.off + 128);
   ctx->phi_all = reinterpret_cast<double*>(w + lay.phi_all.off);
   ctx->bar = reinterpret_cast<unsigned*>(w + lay.bar.off);
+  if (c.zero_phase_memory) ctx->phase = reinterpret_cast<float2*>(w + lay.phase.off);
   ctx->pos_host.assign(positions_host, positions_host + 2 * (size_t)c.n_pos);
 
   auto bail = [&](emagpie_status e) {
@@ -616,6 +634,10 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   if ((e = hipMemcpyAsync(ctx->pos, p2.data(), c.n_pos * sizeof(int2), hipMemcpyHostToDevice, s)) != hipSuccess)
     return hipfail(e, "upload positions");
   if ((e = hipMemsetAsync(ctx->scal_i, 0, 64, s)) != hipSuccess) return hipfail(e, "clear flags");
+  if (ctx->phase &&
+      (e = emg::launch_fill_c64(ctx->phase, (size_t)c.n_pos * c.m * c.m, make_float2(1.f, 0.f), s)) !=
+          hipSuccess)
+    return hipfail(e, "clear phase memory");
   if ((e = emg::launch_layout_intensities(c.m, ctx->layout_plan, intensities_dev, ctx->dperm, c.n_pos,
                                            ctx->phi_all,
                                            ctx->scal_i, s)) != hipSuccess)
@@ -650,6 +672,14 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   ctx->cfg.tune_cache = nullptr;  // the caller's string is only read during init
   *out = ctx;
   g_err.clear();
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_phase_memory_reset(emagpie_ctx ctx, void* stream) {
+  if (!ctx) return fail(EMAGPIE_E_ARG, "null context");
+  if (!ctx->phase) return fail(EMAGPIE_E_ARG, "the context has no phase memory");
+  EMG_HIP(emg::launch_fill_c64(ctx->phase, (size_t)ctx->cfg.n_pos * ctx->cfg.m * ctx->cfg.m,
+                               make_float2(1.f, 0.f), static_cast<hipStream_t>(stream)));
   return EMAGPIE_OK;
 }
 
@@ -751,6 +781,11 @@ emagpie_status emagpie_step_minibatch(emagpie_ctx ctx, void* obj_dev, void* prob
   a.slot = ctx->slots;
   a.b = b;
   a.sampled = sampled_misfit_dev;
+  if (ctx->cfg.path == EMAGPIE_PATH_CHAIN) {
+    if (sampled_misfit_dev) EMG_HIP(emg::launch_zero_doubles(sampled_misfit_dev, 1, s));
+    EMG_HIP(emg::launch_chain_sweep(ctx->cfg.m, ctx->cfg.fft_plan, ctx->cfg.levels, a, b, s));
+    return EMAGPIE_OK;
+  }
   return enqueue_minibatch(ctx, a, ctx->cfg.path == EMAGPIE_PATH_PLAIN, s);
 }
 
@@ -805,6 +840,19 @@ emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, in
       EMG_HIP(hipGraphLaunch(ctx->gexec, s));
       return EMAGPIE_OK;
     }
+    case EMAGPIE_PATH_CHAIN: {
+      if (sampled_misfit_dev) EMG_HIP(emg::launch_zero_doubles(sampled_misfit_dev, 1, s));
+      emg::StepArgs a = base_args(ctx, obj_dev, probe_dev);
+      a.slot = ctx->slots;
+      a.b = 1;
+      a.sampled = sampled_misfit_dev;
+      hipEvent_t e0, e1;
+      EMG_OK(take_pair(ctx, 2, true, &e0, &e1));
+      if (e0) EMG_HIP(hipEventRecord(e0, s));
+      EMG_HIP(emg::launch_chain_sweep(ctx->cfg.m, ctx->cfg.fft_plan, ctx->cfg.levels, a, N, s));
+      if (e1) EMG_HIP(hipEventRecord(e1, s));
+      return EMAGPIE_OK;
+    }
     case EMAGPIE_PATH_PERSISTENT: {
       if (sampled_misfit_dev) EMG_HIP(emg::launch_zero_doubles(sampled_misfit_dev, 1, s));
       emg::StepArgs a = base_args(ctx, obj_dev, probe_dev);
@@ -847,6 +895,7 @@ emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void
   a.b = b;
   a.phi = nullptr;
   a.zplus = static_cast<float2*>(zplus_dev);
+  a.phase_write = 0;  // a diagnostic: reads the phase memory, leaves it as it was
   EMG_HIP(emg::launch_patch_step(ctx->cfg.m, ctx->cfg.fft_plan, ctx->cfg.levels, a, s));
   return EMAGPIE_OK;
 }

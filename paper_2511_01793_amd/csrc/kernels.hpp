@@ -196,7 +196,11 @@ __device__ __forceinline__ void pix_rc(int tid, int e, int& r, int& c) {
 //   load(rd, r0, c0, q, z, R) fills the probe, object window and revised exit
 //   wave of the block at (r0, c0); element 2 i + j is pixel (r0 + i, c0 + j)
 // ---------------------------------------------------------------------------
-template <int M, int V, int L, class LOAD>
+// DIRECT (minibatch of one slot, the whole step in one workgroup): instead of
+// storing numerators for the finalize, apply the finalize's arithmetic here --
+// sums that start from zero, z+ = N / D and Q+ = M / E, the joint step -- and write
+// the object window and the probe in place.  Every pixel has one owner thread.
+template <int M, int V, int L, bool DIRECT = false, class LOAD>
 __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, LOAD load,
                                              float qqmax, float zmax) {
   const size_t base = (size_t)s * M * M;
@@ -259,6 +263,27 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, 
         E[e] = z2 + uz;
       }
     }
+    if constexpr (DIRECT) {
+      const int4 sl = a.slot[s];
+      const cx<float> zero{0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + (e >> 1), c = c0 + (e & 1);
+        const float dd = 0.f + D[e];
+        if (dd > 0.f) {
+          const cx<float> zp = scale(add(zero, N[e]), 1.f / dd);
+          st(a.obj, (size_t)(sl.y + r) * a.n + sl.z + c, a.joint ? aligned_sqrt(zz[e], zp) : zp);
+        }
+        if (a.update_probe) {
+          const float et = 0.f + (slot_den ? zmax : E[e]);
+          if (et > 0.f) {
+            const cx<float> qp = scale(add(zero, Mn[e]), 1.f / et);
+            st(a.probe, (size_t)r * M + c, a.joint ? aligned_sqrt(q[e], qp) : qp);
+          }
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const size_t o = base + (size_t)(r0 + i) * M + c0;
@@ -275,7 +300,7 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, 
     }
   }
   // alpha_z = 1: the probe denominator |z_k|^2 + u_z = max |z_k|^2 is one number per patch
-  if (slot_den && !a.zplus && tid == 0) a.pden_slot[s] = zmax;
+  if (!DIRECT && slot_den && !a.zplus && tid == 0) a.pden_slot[s] = zmax;
 }
 
 // modulus projection of one pixel in transform order: Psi' = a Psi/|Psi|
@@ -284,8 +309,14 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, 
 // instead of a correctly rounded square root and division.  |Psi|^2 below the
 // smallest normal float (|Psi| < 1.1e-19) counts as zero: theta := 0 there.
 // Written with selects only, so no lane branches.
+//
+// With a phase memory ph (the stateful rule stated after Eq. 3), a zero bin takes
+// the unit phasor stored at the pattern's previous visit instead of theta = 0, and
+// a live bin stores its phasor Psi/|Psi| when `write` is set.  The memory starts
+// at (1, 0), which reproduces theta = 0 at the first visit.
 template <int M>
-__device__ __forceinline__ float project_amp(cx<float>& P, float amp) {
+__device__ __forceinline__ float project_amp(cx<float>& P, float amp, float2* ph = nullptr,
+                                             bool write = false) {
   constexpr float kTiny = 1.17549435e-38f;  // FLT_MIN
   constexpr float kInvM2 = 1.f / float(M * M);
   const float p2 = norm2(P);
@@ -293,23 +324,36 @@ __device__ __forceinline__ float project_amp(cx<float>& P, float amp) {
   const float ir = __builtin_amdgcn_rsqf(fmaxf(p2, kTiny));
   const float diff = (live ? p2 * ir : 0.f) - amp;
   const float f = amp * ir * kInvM2;
-  P.re = live ? P.re * f : amp * kInvM2;
-  P.im = live ? P.im * f : 0.f;
+  if (ph) {
+    if (live) {
+      if (write) *ph = make_float2(P.re * ir, P.im * ir);
+      P = cx<float>{P.re * f, P.im * f};
+    } else {
+      const float2 u = *ph;
+      const float s = amp * kInvM2;
+      P = cx<float>{s * u.x, s * u.y};
+    }
+  } else {
+    P.re = live ? P.re * f : amp * kInvM2;
+    P.im = live ? P.im * f : 0.f;
+  }
   return diff * diff;
 }
 // measured amplitude a = sqrt(max(d, 0)) of one intensity (hardware square root,
 // within one ulp)
 __device__ __forceinline__ float amplitude(float d) { return __builtin_amdgcn_sqrtf(fmaxf(d, 0.f)); }
 template <int M>
-__device__ __forceinline__ float project_px(cx<float>& P, float dval) {
-  return project_amp<M>(P, amplitude(dval));
+__device__ __forceinline__ float project_px(cx<float>& P, float dval, float2* ph = nullptr,
+                                            bool write = false) {
+  return project_amp<M>(P, amplitude(dval), ph, write);
 }
 
 // ---------------------------------------------------------------------------
 // the whole patch stage for slot s, LDS-resident
 // ---------------------------------------------------------------------------
-template <int M, int V, int L>
-__device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* A,
+// Returns the slot's sampled misfit (in thread 0).
+template <int M, int V, int L, bool DIRECT = false>
+__device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>* A,
                                            const cx<float>* tws, float* redf, double* redd,
                                            int tid) {
   using P = Px<M, V>;
@@ -364,8 +408,14 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
   fft2_forward_head<float, M, V>(A, tws, tid);
   // last forward pass, modulus projection, first inverse pass, in registers
   double acc = 0.0;
+  float2* ph = a.phase ? a.phase + (size_t)k * M * M : nullptr;
   fft_pass_pair<float, M, V>(A, tid, [&](int e, cx<float>& v) {
-    acc += (double)project_amp<M>(v, amplitude(amp[e]));
+    float2* pe = nullptr;
+    if (ph) {
+      const int w = tid + (e / CP::R1) * CP::NT;
+      pe = ph + (CP::R1 * (w / M) + e % CP::R1) * M + w % M;
+    }
+    acc += (double)project_amp<M>(v, amplitude(amp[e]), pe, a.phase_write != 0);
   });
   acc = wave_sum(acc);
   if ((tid & 63) == 0) redd[tid >> 6] = acc;
@@ -373,7 +423,7 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
   fft2_inverse_tail<float, M, V>(A, tws, tid);
   float qqmax, zmax;
   lds_max2<NT>(redf, qqmax, zmax);
-  pixel_update<M, V, L>(
+  pixel_update<M, V, L, DIRECT>(
       a, s, tid,
       [&](int rd, int r0, int c0, cx<float>* q, cx<float>* zz, cx<float>* Rv) {
 #pragma unroll
@@ -393,8 +443,13 @@ __device__ __forceinline__ void patch_step(const StepArgs& a, int s, cx<float>* 
         }
       },
       qqmax, zmax);
-  if (tid == 0 && a.phi) a.phi[s] = lds_sum<NT>(redd) / (2.0 * M * M);
+  double phi = 0.0;
+  if (tid == 0) {
+    phi = lds_sum<NT>(redd) / (2.0 * M * M);
+    if (a.phi) a.phi[s] = phi;
+  }
   __syncthreads();  // LDS is reused by the next slot of a persistent loop
+  return phi;
 }
 
 // ---------------------------------------------------------------------------
@@ -709,6 +764,36 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_epoch_persistent(StepArgs 
   }
 }
 
+// Sequential sweep of minibatch-1 steps in one workgroup (the paper's literal
+// order: each step sees the previous step's object and probe).  No grid-wide
+// synchronisation: every step touches only its own window and the probe, and the
+// workgroup barrier at the end of each step orders it before the next.  The
+// sampled misfit accumulates exactly as the finalize adds it.
+template <int M, int V, int L>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_sweep_chain(StepArgs a, int n_steps) {
+  __shared__ cx<float> A[M * lds_stride<M>()];
+  __shared__ cx<float> tws[M];
+  __shared__ float redf[32];
+  __shared__ double redd[16];
+  const int tid = threadIdx.x;
+  stage_twiddles<M, Plan<M, V>::NT>(a.tw, tws, tid);
+  __syncthreads();
+  const int4* slots = a.slot;
+  // the running sum stays in a register of thread 0 (the finalize's order:
+  // sampled <- sampled + (0 + phi) after every step), stored once at the end
+  double sampled = (tid == 0 && a.sampled) ? *a.sampled : 0.0;
+  for (int step = 0; step < n_steps; ++step) {
+    StepArgs x = a;
+    x.slot = slots + step;
+    x.b = 1;
+    const double phi = patch_step<M, V, L, true>(x, 0, A, tws, redf, redd, tid);
+    double t = 0.0;
+    t += phi;
+    sampled += t;
+  }
+  if (tid == 0 && a.sampled) *a.sampled = sampled;
+}
+
 // ---------------------------------------------------------------------------
 // plain path: one launch per stage, intermediates in HBM
 // ---------------------------------------------------------------------------
@@ -771,7 +856,8 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_project(StepArgs a) {
     pix_rc<M, V>(tid, e, r, c);
     const size_t o = (size_t)r * M + c;
     cx<float> P = ld(X, o);
-    acc += (double)project_px<M>(P, dk[o]);
+    float2* ph = a.phase ? a.phase + (size_t)a.slot[s].x * M * M + o : nullptr;
+    acc += (double)project_px<M>(P, dk[o], ph, a.phase_write != 0);
     st(X, o, P);
   }
   const double tot = block_sum<NT>(acc, redd, tid);
@@ -1232,6 +1318,18 @@ hipError_t Launchers<M>::numerators(int v, int L, const StepArgs& a, hipStream_t
     return with_levels(L, [&](auto lc) {
       constexpr int V = decltype(vc)::value, LV = decltype(lc)::value;
       hipLaunchKernelGGL((k_numerators<M, V, LV>), dim3(a.b), dim3(Plan<M, V>::NT), 0, s, a);
+      return hipGetLastError();
+    });
+  });
+}
+
+template <int M>
+hipError_t Launchers<M>::chain(int v, int L, const StepArgs& a, int n_steps, hipStream_t s) {
+  return with_plan<M>(v, [&](auto vc) {
+    return with_levels(L, [&](auto lc) {
+      constexpr int V = decltype(vc)::value, LV = decltype(lc)::value;
+      hipLaunchKernelGGL((k_sweep_chain<M, V, LV>), dim3(1), dim3(Plan<M, V>::NT), 0, s, a,
+                         n_steps);
       return hipGetLastError();
     });
   });

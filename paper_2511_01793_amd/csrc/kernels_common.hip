@@ -126,6 +126,9 @@ hipError_t launch_numerators(int m, int v, int L, const StepArgs& a, hipStream_t
 hipError_t launch_surrogate_terms(int m, int v, const StepArgs& a, double* terms, hipStream_t s) {
   EMG_BY_M(m, surrogate(v, a, terms, s));
 }
+hipError_t launch_chain_sweep(int m, int v, int L, const StepArgs& a, int n_steps, hipStream_t s) {
+  EMG_BY_M(m, chain(v, L, a, n_steps, s));
+}
 hipError_t launch_grad(int m, int v, bool f64, const GradArgs& g, hipStream_t s) {
   EMG_BY_M(m, grad(v, f64, g, s));
 }

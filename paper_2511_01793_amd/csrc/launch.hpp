@@ -22,6 +22,8 @@ struct StepArgs {
   int update_probe;
   int joint;         // 1: Eq. 6 joint step; 0: z <- z+, Q <- Q+ (Eq. 2)
   int pgroups;       // slot groups of the probe sums (probe_groups(minibatch))
+  float2* phase;     // nullable: N x m^2 unit phasors of the zero-bin phase rule (transform order)
+  int phase_write;   // 1: store the phasors used (a step); 0: read only
   const float2* tw;  // m twiddles exp(-2 pi i j / m)
   // per-slot products of the patch stage
   float2* numer;     // b x m^2 object numerators conj(Q) R + u z'
@@ -91,6 +93,10 @@ hipError_t launch_layout_intensities(int m, int v, const float* d, float* dperm,
 hipError_t launch_normalize_probe(int m, float2* probe, double dp_avg, int* zero_flag,
                                   hipStream_t s);
 
+// One workgroup runs a whole sequential sweep (minibatch 1): a.slot points at n_steps
+// slots; each step's update is applied directly to the object window and the probe.
+hipError_t launch_chain_sweep(int m, int v, int L, const StepArgs& a, int n_steps, hipStream_t s);
+
 // misfit terms, unreduced: of all patterns (slot == nullptr; count = N, pattern k at
 // pos[k]) or of the count patterns of a slot list -> phi_out (count doubles)
 hipError_t launch_misfit_terms(int m, int v, const float2* obj, int n, const float2* probe,
@@ -150,6 +156,7 @@ struct Launchers {
   static hipError_t numerators(int v, int L, const StepArgs& a, hipStream_t s);
   static hipError_t surrogate(int v, const StepArgs& a, double* terms, hipStream_t s);
   static hipError_t grad(int v, bool f64, const GradArgs& g, hipStream_t s);
+  static hipError_t chain(int v, int L, const StepArgs& a, int n_steps, hipStream_t s);
 };
 
 }  // namespace emg

@@ -16,7 +16,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libemagpie.so")
 
-PATHS = {"plain": 0, "fused": 1, "graph": 2, "persistent": 3, "auto": 4}
+PATHS = {"plain": 0, "fused": 1, "graph": 2, "persistent": 3, "auto": 4, "chain": 5}
 PATH_NAMES = {v: k for k, v in PATHS.items()}
 TUNE = -1  # fft_plan / finalize_shape: choose by timing at init
 F32, F64 = 0, 1
@@ -33,6 +33,7 @@ EXPORTS = [
     "emagpie_version", "emagpie_profile_enable", "emagpie_profile_read",
     "emagpie_group_workspace_size", "emagpie_group_create", "emagpie_group_epoch",
     "emagpie_group_destroy", "emagpie_plan_get", "emagpie_plan_describe", "emagpie_check_step",
+    "emagpie_phase_memory_reset",
 ]
 
 
@@ -50,7 +51,7 @@ class Config(ctypes.Structure):
         ("alpha", ctypes.c_float), ("alpha_z", ctypes.c_float),
         ("update_probe", ctypes.c_int32), ("joint_step", ctypes.c_int32), ("path", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("fft_plan", ctypes.c_int32), ("finalize_shape", ctypes.c_int32),
-        ("tune_cache", ctypes.c_char_p),
+        ("tune_cache", ctypes.c_char_p), ("zero_phase_memory", ctypes.c_int32),
     ]
 
 
@@ -61,7 +62,7 @@ class Plan(ctypes.Structure):
         ("fin_threads", ctypes.c_int32), ("fin_tile", ctypes.c_int32), ("path", ctypes.c_int32),
         ("tuned", ctypes.c_int32), ("n_fft_plans", ctypes.c_int32), ("fft_us", ctypes.c_float * 4),
         ("n_fin_shapes", ctypes.c_int32), ("fin_us", ctypes.c_float * 4),
-        ("path_ms", ctypes.c_float * 4),
+        ("path_ms", ctypes.c_float * 8),
     ]
 
     def as_dict(self) -> dict:
@@ -109,6 +110,7 @@ def lib() -> ctypes.CDLL:
         "emagpie_group_destroy": [vp],
         "emagpie_plan_get": [vp, ctypes.POINTER(Plan)],
         "emagpie_check_step": [vp, vp, vp, vp, i32, vp, vp],
+        "emagpie_phase_memory_reset": [vp, vp],
         "emagpie_plan_describe": [i32, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
@@ -177,7 +179,7 @@ class Reconstruction:
                  levels: int = 1, alpha: float = 0.05, alpha_z: float = 1.0,
                  update_probe: bool = True, joint_step: bool = True, path: str = "graph",
                  seed: int = 0, fft_plan: int = 0, finalize_shape: int = 0,
-                 tune_cache: str | None = None):
+                 tune_cache: str | None = None, zero_phase_memory: bool = False):
         pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32).reshape(-1, 2))
         if intensities.dim() != 3 or intensities.dtype != torch.float32 or not intensities.is_cuda:
             raise ValueError("intensities must be a (N, m, m) float32 CUDA tensor")
@@ -192,7 +194,8 @@ class Reconstruction:
                           path=PATHS[path],
                           seed=int(seed) & ((1 << 64) - 1), fft_plan=int(fft_plan),
                           finalize_shape=int(finalize_shape),
-                          tune_cache=None if tune_cache is None else os.fsencode(tune_cache))
+                          tune_cache=None if tune_cache is None else os.fsencode(tune_cache),
+                          zero_phase_memory=int(bool(zero_phase_memory)))
         nbytes = workspace_size(self.cfg)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=intensities.device)
         base = self._ws.data_ptr()
@@ -271,6 +274,10 @@ class Reconstruction:
             _expect(perm, torch.int32, (self.n_pos,), "perm")
         _check(lib().emagpie_epoch(self._ctx, obj.data_ptr(), probe.data_ptr(), int(epoch),
                                    _ptr(perm), _ptr(sampled), _stream()))
+
+    def reset_phase_memory(self):
+        """Zero-bin phase memory back to the first-sweep state (theta = 0 everywhere)."""
+        _check(lib().emagpie_phase_memory_reset(self._ctx, _stream()))
 
     def check_step(self, obj, probe, idx) -> torch.Tensor:
         """One minibatch update (as step()) that also returns, in float64 on the device,

@@ -81,7 +81,7 @@ def magnitude_error(z, z_true, align_scale: bool = False) -> float:
 
 def reconstruct(problem, *, method: str = "emagpie", levels: int | None = None,
                 max_epochs: int = 300, window: int = 5, patience: int = 10,
-                floor_factor: float | None = None, path: str = "graph", seed: int = 0,
+                floor_factor: float | None = None, path: str = "auto", seed: int = 0,
                 minibatch: int | None = None, record_error: bool = True) -> dict:
     """Run one method on one problem with the paper's stopping rules; returns the history.
 

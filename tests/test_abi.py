@@ -126,3 +126,15 @@ def test_tuning_needs_scratch_state_in_the_workspace():
     tuned = E.workspace_size(cfg(n=256, fft_plan=E.TUNE))
     auto = E.workspace_size(cfg(n=256, path=E.PATHS["auto"]))
     assert tuned == auto >= plain + 256 * 256 * 8
+
+
+def test_sequential_mode_configuration():
+    with pytest.raises(E.EmagpieError) as ei:
+        E.workspace_size(cfg(path=E.PATHS["chain"]))  # minibatch 10
+    assert ei.value.name == "E_ARG"
+    assert E.workspace_size(cfg(path=E.PATHS["chain"], minibatch=1)) > 0
+    with pytest.raises(E.EmagpieError) as ei:
+        E.workspace_size(cfg(zero_phase_memory=2))
+    assert ei.value.name == "E_ARG"
+    # the phase memory holds one complex64 phasor per pattern pixel
+    assert E.workspace_size(cfg(zero_phase_memory=1)) >= E.workspace_size(cfg()) + 100 * 32 * 32 * 8

@@ -445,3 +445,65 @@ def test_permutation_is_valid_and_uniform():
     assert len(counts) == 6
     assert all(abs(c - 1000) < 150 for c in counts.values())
     assert not np.array_equal(O.permutation(1, 0, 50), O.permutation(1, 1, 50))
+
+
+# ------------------------------------------------------------------ stateful zero-bin phase rule
+
+def test_phase_memory_rule_on_exact_zero_bins():
+    """The rule stated after Eq. 3: where F(Q z_k) = 0 the phase is the one pattern k had at
+    its previous iterate (0 at the first).  A constant exit wave has an exact-zero spectrum
+    except at DC, so after a random first visit the second visit's revised wave must carry
+    the first visit's phases at every non-DC bin: F(R) = a exp(i theta_prev) there."""
+    rng = np.random.default_rng(7)
+    m, n = 16, 24
+    a = np.abs(rng.standard_normal((1, m, m))) + 0.5
+    pos = np.array([[3, 5]])
+    mem = np.ones((1, m, m), complex)
+    # first visit: random exit wave, no zero bins -> memory holds its unit phasors
+    Q1 = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    z1 = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Psi1 = O.dft2(Q1 * O.patch(z1, pos[0], m))
+    assert np.all(np.abs(Psi1) > 0)
+    O.step_minibatch(Q1, z1, pos, a, [0], alpha=0.1, phase_mem=mem)
+    np.testing.assert_allclose(mem[0], Psi1 / np.abs(Psi1), atol=1e-14)
+    # second visit: constant exit wave (Q and the window constant)
+    Q2 = np.full((m, m), 0.8 - 0.3j)
+    z2 = np.full((n, n), 1.1 + 0.2j)
+    Psi2 = O.dft2(Q2 * O.patch(z2, pos[0], m))
+    zero = np.abs(Psi2) == 0
+    assert zero.sum() == m * m - 1 and not zero[0, 0]
+    prev = mem[0].copy()
+    _, _, info = O.step_minibatch(Q2, z2, pos, a, [0], alpha=0.1, phase_mem=mem)
+    FR = O.dft2(info["R"][0])
+    np.testing.assert_allclose(np.abs(FR), a[0], rtol=1e-12)
+    np.testing.assert_allclose(FR[zero] / np.abs(FR[zero]), prev[zero], atol=1e-12)
+    np.testing.assert_allclose(FR[0, 0] / abs(FR[0, 0]), Psi2[0, 0] / abs(Psi2[0, 0]), atol=1e-12)
+    # the memory keeps the inherited phases where the bin was zero again, the new one at DC
+    np.testing.assert_allclose(mem[0][zero], prev[zero], atol=0)
+    # without memory the same visit takes theta = 0 at the zero bins
+    R0 = O.revised_exit_wave(Q2, O.patch(z2, pos[0], m), a[0])
+    FR0 = O.dft2(R0)
+    np.testing.assert_allclose(FR0[zero], a[0][zero] + 0j, atol=1e-12)
+
+
+def test_phase_memory_leaves_misfit_and_nonzero_steps_unchanged():
+    # the misfit does not depend on theta at a zero bin (|0 - a e^{i theta}| = a), and a
+    # memory of ones reproduces theta(0) = 0 exactly
+    rng = np.random.default_rng(8)
+    m, n, N = 16, 40, 6
+    pos = rng.integers(0, n - m + 1, size=(N, 2))
+    a = np.abs(rng.standard_normal((N, m, m)))
+    Q = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    q1, z1, i1 = O.step_minibatch(Q, z, pos, a, [0, 2, 5], alpha=0.05, levels=2)
+    mem = np.ones((N, m, m), complex)
+    q2, z2, i2 = O.step_minibatch(Q, z, pos, a, [0, 2, 5], alpha=0.05, levels=2, phase_mem=mem)
+    np.testing.assert_array_equal(q1, q2)
+    np.testing.assert_array_equal(z1, z2)
+    Qc = np.full((m, m), 1.0 + 0j)
+    zc = np.full((n, n), 0.5 + 0.5j)
+    R_a = O.idft2(a[1] * O.phase_used(O.dft2(Qc * O.patch(zc, pos[1], m)), np.exp(1j * rng.uniform(0, 6, (m, m)))))
+    R_b = O.revised_exit_wave(Qc, O.patch(zc, pos[1], m), a[1])
+    e_a = Qc * O.patch(zc, pos[1], m) - R_a
+    e_b = Qc * O.patch(zc, pos[1], m) - R_b
+    assert abs(np.vdot(e_a, e_a).real - np.vdot(e_b, e_b).real) < 1e-9 * np.vdot(e_b, e_b).real
