@@ -53,3 +53,22 @@ def test_check_step_values_and_properties(m, L, b):
             assert out[1] <= out[0] * (1 + 1e-5), out  # Prop. 3.2: sampled surrogate descent
         rec.epoch(obj, probe, 20 + stage)
     rec.close()
+
+
+def test_prop32_descent_at_every_step_of_a_sweep():
+    """Prop. 3.2 on the GPU at scale: single-position, single-level steps through a whole
+    sweep of a 256^2 object (169 positions, 64^2 probe); every step must lower the sampled
+    surrogate, and the misfit after must stay below the surrogate (majorisation)."""
+    p = problem("tiny", n=256, m=64, scan=("raster", 13, 15, 1), photons=1e6, B=1, L=1,
+                alpha=0.05, seed=71)
+    print("case: prop 3.2 sweep", p.n_pos, flush=True)
+    rec = make_rec(p, path="fused", minibatch=1, levels=1)
+    obj, probe = init_state(p, rec)
+    rec.epoch(obj, probe, 0)
+    order = O.permutation(9, 1, p.n_pos)
+    outs = torch.stack([rec.check_step(obj, probe, [int(k)]) for k in order]).cpu().numpy()
+    before, surr, after = outs[:, 0], outs[:, 1], outs[:, 2]
+    assert np.all(surr <= before * (1 + 1e-5)), np.max(surr / before)
+    assert np.all(after <= surr * (1 + 1e-5)), np.max(after / surr)
+    assert np.mean(surr < before) > 0.95
+    rec.close()
