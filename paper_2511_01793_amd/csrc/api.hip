@@ -65,7 +65,7 @@ bool wants_tuning(const emagpie_config& c) {
 
 struct Layout {
   Region dperm, pos, slots, tw32, tw64, numer, pnum, pden, pden_slot, phi, stack, zmax, ubuf, Dbuf, scal,
-      bar, phi_all, gz, gq, tune_obj, tune_probe, phase;
+      bar, phi_all, gz, gq, tune_obj, tune_probe, phase, part;
   int grad_chunk;
   size_t total;
 };
@@ -98,7 +98,7 @@ Layout make_layout(const emagpie_config& c) {
   L.scal = take(256);
   L.bar = take(256);
   L.phi_all = take(N * 8);
-  L.grad_chunk = (int)std::min<size_t>(N, c.m == 128 ? 256 : emg::kMaxSlots);
+  L.grad_chunk = c.m == 256 ? 0 : (int)std::min<size_t>(N, c.m == 128 ? 256 : emg::kMaxSlots);
   const size_t gel = c.m <= 64 ? 16 : 8;  // complex128 where the float64 gradient exists
   L.gz = take((size_t)L.grad_chunk * m2 * gel);
   L.gq = take((size_t)L.grad_chunk * m2 * gel);
@@ -107,14 +107,16 @@ Layout make_layout(const emagpie_config& c) {
   L.tune_obj = take(tune ? (size_t)c.n * c.n * 8 : 0);
   L.tune_probe = take(tune ? m2 * 8 : 0);
   L.phase = take(c.zero_phase_memory ? N * m2 * 8 : 0);
+  // m = 256: strip maxima and column-block partial misfits per slot (16 of each)
+  L.part = take(c.m == 256 ? B * 16 * (4 + 4 + 8) : 0);
   L.total = cur;
   return L;
 }
 
 emagpie_status check_config(const emagpie_config* c) {
   if (!c) return fail(EMAGPIE_E_ARG, "null config");
-  if (c->m != 32 && c->m != 64 && c->m != 128)
-    return fail(EMAGPIE_E_SHAPE, "probe side m must be 32, 64 or 128");
+  if (c->m != 32 && c->m != 64 && c->m != 128 && c->m != 256)
+    return fail(EMAGPIE_E_SHAPE, "probe side m must be 32, 64, 128 or 256");
   if (c->n < c->m || c->n > 65536) return fail(EMAGPIE_E_SHAPE, "object side n must satisfy m <= n <= 65536");
   if (c->n_pos < 1) return fail(EMAGPIE_E_SHAPE, "n_pos must be >= 1");
   if (c->minibatch < 1 || c->minibatch > emg::kMaxSlots)
@@ -131,6 +133,9 @@ emagpie_status check_config(const emagpie_config* c) {
     return fail(EMAGPIE_E_ARG, "the chain path needs minibatch 1");
   if (c->zero_phase_memory != 0 && c->zero_phase_memory != 1)
     return fail(EMAGPIE_E_ARG, "zero_phase_memory must be 0 or 1");
+  if (c->m == 256 && c->path != EMAGPIE_PATH_FUSED && c->path != EMAGPIE_PATH_GRAPH &&
+      c->path != EMAGPIE_PATH_AUTO)
+    return fail(EMAGPIE_E_UNSUPPORTED, "m = 256 runs the fused and graph paths only");
   if (c->fft_plan != EMAGPIE_TUNE && (c->fft_plan < 0 || c->fft_plan >= emg::fft_plan_count(c->m)))
     return fail(EMAGPIE_E_ARG, "fft_plan must be EMAGPIE_TUNE or in [0, " +
                                    std::to_string(emg::fft_plan_count(c->m)) + ") for this m");
@@ -198,6 +203,13 @@ emg::StepArgs base_args(emagpie_ctx c, void* obj, void* probe) {
   a.pgroups = emg::probe_groups(c->cfg.minibatch);
   a.phase = c->phase;
   a.phase_write = 1;
+  if (c->cfg.m == 256) {
+    uint8_t* p = c->ws + c->lay.part.off;
+    const size_t B = (size_t)c->cfg.minibatch;
+    a.part_q = reinterpret_cast<float*>(p);
+    a.part_z = reinterpret_cast<float*>(p + B * 16 * 4);
+    a.part_phi = reinterpret_cast<double*>(p + B * 16 * 8);
+  }
   a.tw = c->tw32;
   a.numer = c->numer;
   a.pnum = c->pnum;
@@ -496,6 +508,7 @@ emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* i
     int best = EMAGPIE_PATH_FUSED;
     for (int p : cand) {
       if (p == EMAGPIE_PATH_CHAIN && B != 1) continue;
+      if (m == 256 && p != EMAGPIE_PATH_FUSED && p != EMAGPIE_PATH_GRAPH) continue;
       c->cfg.path = p;
       float ms = -1.f;
       int64_t epoch = 0;
@@ -906,6 +919,7 @@ emagpie_status emagpie_check_step(emagpie_ctx ctx, void* obj_dev, void* probe_de
   if (!ctx || !obj_dev || !probe_dev || !batch_idx_dev || !out3_dev)
     return fail(EMAGPIE_E_ARG, "null argument");
   if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
+  if (ctx->cfg.m == 256) return fail(EMAGPIE_E_UNSUPPORTED, "no descent check for m = 256");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int m = ctx->cfg.m, v = ctx->cfg.fft_plan;
   EMG_HIP(emg::launch_slot_info(batch_idx_dev, ctx->pos, ctx->cfg.n_pos, ctx->slots, b, s));
@@ -932,6 +946,16 @@ emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* 
                               double* misfit_dev, void* stream) {
   if (!ctx || !obj_dev || !probe_dev || !misfit_dev) return fail(EMAGPIE_E_ARG, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->cfg.m == 256) {
+    // strips and column blocks over the stack buffer, minibatch-sized chunks of patterns
+    const emg::StepArgs a = base_args(ctx, const_cast<void*>(obj_dev), const_cast<void*>(probe_dev));
+    for (int k0 = 0; k0 < ctx->cfg.n_pos; k0 += ctx->cfg.minibatch) {
+      const int cnt = std::min(ctx->cfg.minibatch, ctx->cfg.n_pos - k0);
+      EMG_HIP(emg::launch_misfit_strips(256, a, k0, cnt, ctx->phi_all + k0, s));
+    }
+    EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
+    return EMAGPIE_OK;
+  }
   EMG_HIP(emg::launch_misfit_terms(ctx->cfg.m, ctx->cfg.fft_plan, static_cast<const float2*>(obj_dev),
                                    ctx->cfg.n, static_cast<const float2*>(probe_dev), ctx->dperm,
                                    ctx->pos, nullptr, ctx->cfg.n_pos, ctx->tw32, ctx->phi_all, s));
@@ -947,6 +971,7 @@ emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* pr
   if (dtype != EMAGPIE_F32 && dtype != EMAGPIE_F64) return fail(EMAGPIE_E_ARG, "dtype must be F32 or F64");
   const bool f64 = dtype == EMAGPIE_F64;
   if (f64 && ctx->cfg.m > 64) return fail(EMAGPIE_E_UNSUPPORTED, "float64 gradient needs m <= 64");
+  if (ctx->cfg.m == 256) return fail(EMAGPIE_E_UNSUPPORTED, "no gradient for m = 256");
   hipStream_t s = static_cast<hipStream_t>(stream);
   emg::GradArgs g{};
   g.obj = obj_dev;
@@ -996,6 +1021,7 @@ emagpie_status plan_group(int32_t n_inst, const emagpie_ctx* ctxs, GroupLayout* 
   size_t nslots = 0;
   for (int i = 0; i < n_inst; ++i) {
     if (!ctxs[i]) return fail(EMAGPIE_E_ARG, "null context in group");
+    if (ctxs[i]->cfg.m == 256) return fail(EMAGPIE_E_UNSUPPORTED, "group members need m <= 128");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return fail(EMAGPIE_E_ARG, "a context appears twice in the group");
     const emagpie_config& c = ctxs[i]->cfg;

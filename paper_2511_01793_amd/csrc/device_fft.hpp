@@ -289,6 +289,78 @@ __device__ __forceinline__ void fft_pass_pair(cx<T>* A, int tid, F f) {
   }
 }
 
+// The same passes over a block of LINES independent length-N lines (a strip of
+// rows or a block of columns of a tile too large for one workgroup's LDS).
+// COLS = false: line l holds A[l * LS + p]; COLS = true: A[p * LS + l].
+template <typename T, int N, int R1, int R2, int LINES, int NT, int LS, bool INV, bool STRIDED,
+          bool COLS>
+__device__ __forceinline__ void fft_pass_lines(cx<T>* A, const cx<T>* tw, int tid) {
+  constexpr int R = STRIDED ? R2 : R1;
+  constexpr int G = STRIDED ? R1 : R2;
+  constexpr int ITEMS = LINES * G;
+  static_assert(R1 * R2 == N, "radix split");
+  static_assert(ITEMS % NT == 0 || NT % ITEMS == 0, "items per thread");
+  constexpr int IT = ITEMS >= NT ? ITEMS / NT : 1;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int w = tid + it * NT;
+    if (ITEMS < NT && w >= ITEMS) break;
+    const int line = w % LINES;
+    const int g = w / LINES;
+    cx<T> v[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int p = STRIDED ? (g + R1 * j) : (R1 * g + j);
+      v[j] = A[COLS ? (p * LS + line) : (line * LS + p)];
+    }
+    if (STRIDED && INV) {
+#pragma unroll
+      for (int j = 1; j < R; ++j) v[j] = mul_fma(conjg(tw[g * j]), v[j]);
+    }
+    dft_small<T, INV, R, N>(v, tw);
+    if (STRIDED && !INV) {
+#pragma unroll
+      for (int j = 1; j < R; ++j) v[j] = mul_fma(tw[g * j], v[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int p = STRIDED ? (g + R1 * j) : (R1 * g + j);
+      A[COLS ? (p * LS + line) : (line * LS + p)] = v[j];
+    }
+  }
+}
+
+// Contiguous pass forward, f(point, value) on each transformed value, contiguous
+// pass inverse, in registers (the block form of fft_pass_pair; same items).
+// Point e of a thread is item it = e / R1, j = e % R1 at line (tid + it NT) % LINES,
+// position R1 ((tid + it NT) / LINES) + j.
+template <typename T, int N, int R1, int R2, int LINES, int NT, int LS, bool COLS, class F>
+__device__ __forceinline__ void fft_pass_lines_pair(cx<T>* A, int tid, F f) {
+  constexpr int ITEMS = LINES * R2;
+  constexpr int IT = ITEMS >= NT ? ITEMS / NT : 1;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int w = tid + it * NT;
+    if (ITEMS < NT && w >= ITEMS) break;
+    const int line = w % LINES, g = w / LINES;
+    cx<T> v[R1];
+#pragma unroll
+    for (int j = 0; j < R1; ++j) {
+      const int p = R1 * g + j;
+      v[j] = A[COLS ? (p * LS + line) : (line * LS + p)];
+    }
+    dft_small<T, false, R1, N>(v, nullptr);
+#pragma unroll
+    for (int j = 0; j < R1; ++j) f(it * R1 + j, v[j]);
+    dft_small<T, true, R1, N>(v, nullptr);
+#pragma unroll
+    for (int j = 0; j < R1; ++j) {
+      const int p = R1 * g + j;
+      A[COLS ? (p * LS + line) : (line * LS + p)] = v[j];
+    }
+  }
+}
+
 // Inverse 2-D DFT without the 1/m^2 factor: transform order in, natural out.
 template <typename T, int M, int V>
 __device__ __forceinline__ void fft2_inverse(cx<T>* A, const cx<T>* tw, int tid) {

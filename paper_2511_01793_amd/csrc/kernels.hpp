@@ -200,15 +200,24 @@ __device__ __forceinline__ void pix_rc(int tid, int e, int& r, int& c) {
 // storing numerators for the finalize, apply the finalize's arithmetic here --
 // sums that start from zero, z+ = N / D and Q+ = M / E, the joint step -- and write
 // the object window and the probe in place.  Every pixel has one owner thread.
-template <int M, int V, int L, bool DIRECT = false, class LOAD>
-__device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, LOAD load,
-                                             float qqmax, float zmax) {
+// LY gives the thread's 2 x 2 blocks: LY::ROUNDS and LY::origin(tid, rd, r0, c0) in
+// patch coordinates, to which row0 is added (a strip of a larger patch).
+template <int M, int V>
+struct PxLayout {
+  static constexpr int ROUNDS = Px<M, V>::ROUNDS;
+  __device__ static void origin(int tid, int rd, int& r0, int& c0) { blk_origin<M, V>(tid, rd, r0, c0); }
+};
+
+template <int M, class LY, int L, bool DIRECT, class LOAD>
+__device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int tid, int row0,
+                                                LOAD load, float qqmax, float zmax) {
   const size_t base = (size_t)s * M * M;
   const bool slot_den = a.pden_slot != nullptr;
 #pragma unroll
-  for (int rd = 0; rd < Px<M, V>::ROUNDS; ++rd) {
+  for (int rd = 0; rd < LY::ROUNDS; ++rd) {
     int r0, c0;
-    blk_origin<M, V>(tid, rd, r0, c0);
+    LY::origin(tid, rd, r0, c0);
+    r0 += row0;
     cx<float> q[4], zz[4], R[4];
     load(rd, r0, c0, q, zz, R);
     // per pixel: |Q|^2, u, D = |Q|^2 + u, conj(Q) R (shared by the coarse-grid residual
@@ -301,6 +310,12 @@ __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, 
   }
   // alpha_z = 1: the probe denominator |z_k|^2 + u_z = max |z_k|^2 is one number per patch
   if (!DIRECT && slot_den && !a.zplus && tid == 0) a.pden_slot[s] = zmax;
+}
+
+template <int M, int V, int L, bool DIRECT = false, class LOAD>
+__device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, LOAD load,
+                                             float qqmax, float zmax) {
+  pixel_update_ly<M, PxLayout<M, V>, L, DIRECT>(a, s, tid, 0, load, qqmax, zmax);
 }
 
 // modulus projection of one pixel in transform order: Psi' = a Psi/|Psi|

@@ -71,6 +71,7 @@ hipError_t launch_fill_c64(float2* p, size_t count, float2 v, hipStream_t s) {
     case 32: return Launchers<32>::CALL;         \
     case 64: return Launchers<64>::CALL;         \
     case 128: return Launchers<128>::CALL;       \
+    case 256: return Launchers256::CALL;         \
     default: return hipErrorInvalidValue;        \
   }
 
@@ -128,6 +129,11 @@ hipError_t launch_surrogate_terms(int m, int v, const StepArgs& a, double* terms
 }
 hipError_t launch_chain_sweep(int m, int v, int L, const StepArgs& a, int n_steps, hipStream_t s) {
   EMG_BY_M(m, chain(v, L, a, n_steps, s));
+}
+hipError_t launch_misfit_strips(int m, const StepArgs& a, int k0, int count, double* phi_out,
+                                hipStream_t s) {
+  if (m != 256) return hipErrorInvalidValue;
+  return Launchers256::misfit_strips(a, k0, count, phi_out, s);
 }
 hipError_t launch_grad(int m, int v, bool f64, const GradArgs& g, hipStream_t s) {
   EMG_BY_M(m, grad(v, f64, g, s));

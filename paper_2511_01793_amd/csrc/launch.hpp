@@ -22,6 +22,9 @@ struct StepArgs {
   int update_probe;
   int joint;         // 1: Eq. 6 joint step; 0: z <- z+, Q <- Q+ (Eq. 2)
   int pgroups;       // slot groups of the probe sums (probe_groups(minibatch))
+  float* part_q;     // m = 256: per (slot, row strip) max |Q|^2 and max |z_k|^2,
+  float* part_z;     //   per (slot, column block) partial misfit sums
+  double* part_phi;
   float2* phase;     // nullable: N x m^2 unit phasors of the zero-bin phase rule (transform order)
   int phase_write;   // 1: store the phasors used (a step); 0: read only
   const float2* tw;  // m twiddles exp(-2 pi i j / m)
@@ -129,6 +132,11 @@ struct GradArgs {
 };
 hipError_t launch_grad(int m, int v, bool f64, const GradArgs& g, hipStream_t s);
 
+// m = 256 misfit terms of patterns k0 .. k0 + count - 1 (count <= the context's
+// minibatch; uses a.stack and the part_* buffers) -> phi_out[0 .. count)
+hipError_t launch_misfit_strips(int m, const StepArgs& a, int k0, int count, double* phi_out,
+                                hipStream_t s);
+
 // The launchers of one probe side (kernels.hpp; instantiated per side in
 // kernels_m32.hip, kernels_m64.hip and kernels_m128.hip).
 template <int M>
@@ -157,6 +165,39 @@ struct Launchers {
   static hipError_t surrogate(int v, const StepArgs& a, double* terms, hipStream_t s);
   static hipError_t grad(int v, bool f64, const GradArgs& g, hipStream_t s);
   static hipError_t chain(int v, int L, const StepArgs& a, int n_steps, hipStream_t s);
+};
+
+// m = 256 (kernels256.hpp, kernels_m256.hip): the same members; the tile exceeds
+// LDS, so a patch runs as row strips and column blocks over a.stack.  Members with
+// no m = 256 form return hipErrorInvalidValue (the host rejects those requests
+// before launching).
+struct Launchers256 {
+  static hipError_t patch_step(int v, int L, const StepArgs& a, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1);
+  static hipError_t finalize(int f, const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+  static hipError_t patch_step_multi(int v, int L, const StepArgs* args, const int2* work,
+                                     int blocks, hipStream_t s);
+  static hipError_t finalize_multi(int f, const StepArgs* args, const int2* work, int blocks,
+                                   hipStream_t s);
+  static hipError_t finalize_item_count(int f, int n, int pgroups, int* items);
+  static hipError_t plain_step(int v, int L, const StepArgs& a, hipStream_t s);
+  static hipError_t persistent_grid_size(int v, int L, int num_cus, int* grid);
+  static hipError_t persistent_epoch(int v, int L, const StepArgs& a, int n_pos, int B, int grid,
+                                     unsigned* bar, unsigned bar_base, int* err, int* used_grid,
+                                     hipStream_t s);
+  static hipError_t layout(int v, const float* d, float* dperm, int n_pos, double* sums, int* bad,
+                           hipStream_t s);
+  static hipError_t normalize(float2* probe, double dp_avg, int* flag, hipStream_t s);
+  static hipError_t misfit(int v, const float2* obj, int n, const float2* probe, const float* dperm,
+                           const int2* pos, const int4* slot, int count, const float2* tw,
+                           double* phi_out, hipStream_t s);
+  static hipError_t revised_waves(int v, const StepArgs& a, hipStream_t s);
+  static hipError_t numerators(int v, int L, const StepArgs& a, hipStream_t s);
+  static hipError_t surrogate(int v, const StepArgs& a, double* terms, hipStream_t s);
+  static hipError_t grad(int v, bool f64, const GradArgs& g, hipStream_t s);
+  static hipError_t chain(int v, int L, const StepArgs& a, int n_steps, hipStream_t s);
+  static hipError_t misfit_strips(const StepArgs& a, int k0, int count, double* phi_out,
+                                  hipStream_t s);
 };
 
 }  // namespace emg

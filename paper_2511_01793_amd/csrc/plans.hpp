@@ -27,11 +27,14 @@ template <> struct Plan<64, 3> { static constexpr int R1 = 8, R2 = 8, NT = 512; 
 template <> struct Plan<128, 0> { static constexpr int R1 = 16, R2 = 8, NT = 1024; };
 template <> struct Plan<128, 1> { static constexpr int R1 = 8, R2 = 16, NT = 1024; };
 template <> struct Plan<128, 2> { static constexpr int R1 = 16, R2 = 8, NT = 512; };
+// m = 256: the tile exceeds LDS; strips of 16 lines per workgroup (see kernels256.hpp)
+template <> struct Plan<256, 0> { static constexpr int R1 = 16, R2 = 16, NT = 256; };
 
 template <int M> struct PlanCount;
 template <> struct PlanCount<32> { static constexpr int value = 2; };
 template <> struct PlanCount<64> { static constexpr int value = 4; };
 template <> struct PlanCount<128> { static constexpr int value = 3; };
+template <> struct PlanCount<256> { static constexpr int value = 1; };
 
 constexpr int kMaxFftPlans = 4;
 
@@ -42,7 +45,8 @@ inline bool fft_plan_desc(int m, int v, int* r1, int* r2, int* nt) {
   };
   static const D t[] = {{32, 0, 8, 4, 256},   {32, 1, 4, 8, 256},   {64, 0, 8, 8, 1024},
                         {64, 1, 16, 4, 1024}, {64, 2, 4, 16, 1024}, {64, 3, 8, 8, 512},
-                        {128, 0, 16, 8, 1024}, {128, 1, 8, 16, 1024}, {128, 2, 16, 8, 512}};
+                        {128, 0, 16, 8, 1024}, {128, 1, 8, 16, 1024}, {128, 2, 16, 8, 512},
+                        {256, 0, 16, 16, 256}};
   for (const D& d : t)
     if (d.m == m && d.v == v) {
       *r1 = d.r1;
@@ -52,7 +56,7 @@ inline bool fft_plan_desc(int m, int v, int* r1, int* r2, int* nt) {
     }
   return false;
 }
-inline int fft_plan_count(int m) { return m == 32 ? 2 : m == 64 ? 4 : m == 128 ? 3 : 0; }
+inline int fft_plan_count(int m) { return m == 32 ? 2 : m == 64 ? 4 : m == 128 ? 3 : m == 256 ? 1 : 0; }
 
 // finalize shapes: (threads per item, object tile side)
 template <int F> struct FinShape;

@@ -38,7 +38,7 @@ def cfg(**kw):
 
 
 @pytest.mark.parametrize("bad, status", [
-    (dict(m=48), "E_SHAPE"), (dict(m=16), "E_SHAPE"), (dict(n=16), "E_SHAPE"),
+    (dict(m=48), "E_SHAPE"), (dict(m=16), "E_SHAPE"), (dict(m=512), "E_SHAPE"), (dict(n=16), "E_SHAPE"),
     (dict(levels=0), "E_SHAPE"), (dict(levels=4), "E_SHAPE"), (dict(minibatch=0), "E_SHAPE"),
     (dict(minibatch=2048), "E_SHAPE"), (dict(n_pos=0), "E_SHAPE"),
     (dict(alpha=float("nan")), "E_ARG"), (dict(alpha=-1.0), "E_ARG"), (dict(alpha_z=float("inf")), "E_ARG"),
@@ -138,3 +138,17 @@ def test_sequential_mode_configuration():
     assert ei.value.name == "E_ARG"
     # the phase memory holds one complex64 phasor per pattern pixel
     assert E.workspace_size(cfg(zero_phase_memory=1)) >= E.workspace_size(cfg()) + 100 * 32 * 32 * 8
+
+
+def test_probe_side_256_configuration():
+    d = E.plan_describe(256, 0, 0)
+    assert (d["r1"], d["r2"], d["threads"], d["fft_plans"]) == (16, 16, 256, 1)
+    for path in ("fused", "graph", "auto"):
+        assert E.workspace_size(cfg(m=256, n=300, path=E.PATHS[path])) > 100 * 256 * 256 * 4
+    for path in ("plain", "persistent"):
+        with pytest.raises(E.EmagpieError) as ei:
+            E.workspace_size(cfg(m=256, n=300, path=E.PATHS[path]))
+        assert ei.value.name == "E_UNSUPPORTED"
+    with pytest.raises(E.EmagpieError) as ei:
+        E.workspace_size(cfg(m=256, n=200, path=1))
+    assert ei.value.name == "E_SHAPE"

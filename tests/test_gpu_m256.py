@@ -1,0 +1,139 @@
+"""Probe side m = 256 (row strips and column blocks over the stack buffer) against the oracle,
+and the requests this size does not support."""
+import numpy as np
+import pytest
+
+from oracle import emagpie_oracle as O
+from gpu_helpers import EPOCH_TOL, MISFIT_TOL, STEP_TOL, amps, host, init_state, make_rec, problem, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+E = pytest.importorskip("paper_2511_01793_amd.emagpie")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def big(L=2, B=4, n=300, side=3, photons=1e8, seed=81):
+    step = (n - 256 - 2) // (side - 1)
+    return problem("tiny", n=n, m=256, scan=("raster", side, step, 1), photons=photons, B=B, L=L,
+                   alpha=0.05, seed=seed)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+def test_m256_step_parity(L):
+    p = big(L=L)
+    say("case: m256 step", L)
+    rec = make_rec(p, path="fused")
+    obj, probe = init_state(p, rec)
+    rec.epoch(obj, probe, 30)  # leave the phase-free initial guess
+    a = amps(p)
+    idx = np.array([4, 0, 7, 2], dtype=np.int32)
+    z0, q0 = host(obj), host(probe)
+    sampled = torch.zeros((), dtype=torch.float64, device="cuda")
+    rec.step(obj, probe, idx, sampled=sampled)
+    phi = rec.misfit(obj, probe)
+    torch.cuda.synchronize()
+    q1, z1, info = O.step_minibatch(q0, z0, p.positions, a, idx, alpha=p.alpha, levels=L)
+    assert rel(host(obj), z1) < STEP_TOL, rel(host(obj), z1)
+    assert rel(host(probe), q1) < STEP_TOL, rel(host(probe), q1)
+    s = info["sampled_misfit"]
+    assert abs(float(sampled.item()) - s) <= MISFIT_TOL * s
+    ref = O.misfit(host(probe), host(obj), p.positions, a)
+    assert abs(float(phi.item()) - ref) <= MISFIT_TOL * ref
+    rec.close()
+
+
+def test_m256_epochs_fused_graph_bitwise_and_oracle_parity():
+    p = big(L=2, B=4)  # 9 positions: minibatches of 4, 4 and a ragged 1
+    say("case: m256 epochs")
+    a = amps(p)
+    finals = []
+    for path in ("fused", "graph"):
+        rec = make_rec(p, path=path, seed=13)
+        obj, probe = init_state(p, rec)
+        rec.epoch(obj, probe, 0)
+        z0, q0 = host(obj), host(probe)
+        s = torch.zeros((), dtype=torch.float64, device="cuda")
+        rec.epoch(obj, probe, 1, sampled=s)
+        torch.cuda.synchronize()
+        if path == "fused":
+            q1, z1, samp = O.run_epoch(q0, z0, p.positions, a, seed=13, epoch=1, minibatch=4,
+                                       alpha=p.alpha, levels=2)
+            assert rel(host(obj), z1) < EPOCH_TOL and rel(host(probe), q1) < EPOCH_TOL
+            assert abs(float(s.item()) - samp) <= MISFIT_TOL * samp
+        finals.append((obj.clone(), probe.clone(), float(s.item())))
+        rec.close()
+    assert torch.equal(finals[0][0], finals[1][0]) and torch.equal(finals[0][1], finals[1][1])
+    assert finals[0][2] == finals[1][2]
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_m256_mg_cycle_parity(L):
+    p = big(L=L)
+    say("case: m256 mg_cycle", L)
+    rec = make_rec(p, path="fused")
+    obj, probe = init_state(p, rec)
+    rec.epoch(obj, probe, 5)
+    idx = [3, 8]
+    zp = rec.mg_cycle(obj, probe, idx)
+    torch.cuda.synchronize()
+    z0, q0 = host(obj), host(probe)
+    a = amps(p)
+    u = O.probe_regulariser(q0, p.alpha)
+    for j, k in enumerate(idx):
+        r0, c0 = p.positions[k]
+        zk = z0[r0:r0 + 256, c0:c0 + 256]
+        R = O.revised_exit_wave(q0, zk, a[k])
+        assert rel(host(zp[j]), O.magpie_object_step(q0, zk, R, u, L)) < STEP_TOL, k
+    rec.close()
+
+
+def test_m256_phase_memory_and_autotune():
+    p = big(L=1, B=1)
+    say("case: m256 phase memory")
+    k = 4
+    rng = np.random.default_rng(9)
+    Qr = (rng.standard_normal((256, 256)) + 1j * rng.standard_normal((256, 256))).astype(np.complex64)
+    zr = (rng.standard_normal((p.n, p.n)) + 1j * rng.standard_normal((p.n, p.n))).astype(np.complex64)
+    Qc = np.full((256, 256), 0.6 - 0.2j, dtype=np.complex64)
+    zc = np.full((p.n, p.n), 1.0 + 0.1j, dtype=np.complex64)
+    a = amps(p)
+    mem = np.ones((p.n_pos, 256, 256), complex)
+    O.step_minibatch(Qr.astype(complex), zr.astype(complex), p.positions, a, [k], alpha=p.alpha,
+                     phase_mem=mem)
+    q_ref, z_ref, _ = O.step_minibatch(Qc.astype(complex), zc.astype(complex), p.positions, a, [k],
+                                       alpha=p.alpha, phase_mem=mem)
+    rec = make_rec(p, path="auto", minibatch=1)
+    assert rec.plan["path"] in ("fused", "graph") and set(rec.plan["path_ms"]) == {"fused", "graph"}
+    rec.close()
+    d = torch.from_numpy(p.intensities).cuda()
+    rec = E.Reconstruction(p.positions, d, p.n, minibatch=1, levels=1, alpha=p.alpha, path="fused",
+                           zero_phase_memory=True)
+    obj, probe = torch.from_numpy(zr).cuda(), torch.from_numpy(Qr).cuda()
+    rec.step(obj, probe, [k])
+    obj.copy_(torch.from_numpy(zc))
+    probe.copy_(torch.from_numpy(Qc))
+    rec.step(obj, probe, [k])
+    torch.cuda.synchronize()
+    assert rel(host(obj), z_ref) < STEP_TOL and rel(host(probe), q_ref) < STEP_TOL
+    rec.close()
+
+
+def test_m256_unsupported_requests_are_rejected():
+    p = big(L=1, B=2)
+    say("case: m256 unsupported")
+    for path in ("plain", "persistent"):
+        with pytest.raises(E.EmagpieError) as ei:
+            make_rec(p, path=path)
+        assert ei.value.name == "E_UNSUPPORTED"
+    rec = make_rec(p, path="fused")
+    obj, probe = init_state(p, rec)
+    for call in (lambda: rec.grad(obj, probe), lambda: rec.check_step(obj, probe, [0]),
+                 lambda: E.Group([rec])):
+        with pytest.raises(E.EmagpieError) as ei:
+            call()
+        assert ei.value.name == "E_UNSUPPORTED"
+    rec.close()
