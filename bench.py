@@ -36,6 +36,8 @@ WORKLOADS = {
           "minibatch 64, 2 multigrid levels",
     "c3": "1024^2 object, 128^2 probe, 10000-point Fermat spiral, Poisson 1e7 photons, minibatch 256, "
           "3 multigrid levels",
+    "c6": "1024^2 object, 256^2 probe, 31x31 jittered raster (961 positions), Poisson 1e8 photons, "
+          "minibatch 32, 2 multigrid levels",
 }
 
 
@@ -146,7 +148,7 @@ def cpu_baseline(p, budget_s=10.0):
         nb += 1
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nb} consecutive minibatches of 64 ({done} patterns) of the same workload, "
+            "sample": f"{nb} consecutive minibatches of {p.minibatch} ({done} patterns) of the same workload, "
                       f"FP64 NumPy, single thread, {dt:.1f} s"}
 
 
@@ -235,9 +237,10 @@ def main():
                     help="fix the FFT plan, finalize shape and path of the tuned leg instead of "
                          "autotuning (e.g. 3,1,fused; for profiler runs, whose timing distorts "
                          "the autotuner)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
-                    help="c2 (default, the headline workload) or c3 (1024^2 object, 128^2 probe, "
-                         "10000-point Fermat spiral, minibatch 256, 3 levels)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "c6"],
+                    help="c2 (default, the headline workload), c3 (1024^2 object, 128^2 probe, "
+                         "10000-point Fermat spiral, minibatch 256, 3 levels), c5 (16 uneven "
+                         "instances) or c6 (256^2 patterns, 961 positions, minibatch 32)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
@@ -269,7 +272,9 @@ def main():
 
     # every launch strategy with the default kernel plan
     paths = {}
-    for path in ["plain", "fused", "graph", "persistent"]:
+    # m = 256 has no plain or persistent form
+    legs = ["fused", "graph"] if m == 256 else ["plain", "fused", "graph", "persistent"]
+    for path in legs:
         rec, obj, probe = fresh(path)
         t = time_epochs(rec, obj, probe, K, W)
         paths[path] = {"ms_per_epoch": t * 1e3, "patterns_per_s": N / t}
@@ -291,7 +296,7 @@ def main():
         f"(r1 {plan['r1']}, r2 {plan['r2']}, {plan['threads']} threads), finalize shape "
         f"{plan['finalize_shape']}, path {plan['path']}; patch us {plan['fft_us']}, "
         f"finalize us {plan['fin_us']}, path ms {plan['path_ms']}")
-    cands = {("default", k): paths[k] for k in ("fused", "graph", "persistent")}
+    cands = {("default", k): paths[k] for k in ("fused", "graph", "persistent") if k in paths}
     cands[("tuned", plan["path"])] = tuned
     best_key = max(cands, key=lambda k: cands[k]["patterns_per_s"])
     best = best_key[1]
@@ -320,7 +325,8 @@ def main():
         unit_desc = f"one epoch ({len(U)} minibatches)"
     else:
         ms, cnt = prof["patch"]
-        kname = f"k_patch_step<{m}, {bv}, {p.levels}>"
+        kname = (f"k_patch_step<{m}, {bv}, {p.levels}>" if m < 256 else
+                 f"k256_rows_fwd + k256_cols<true> + k256_rows_inv<{p.levels}>")
         bytes_per_launch = N * m * m * 12 / len(U)
         unit_desc = f"one minibatch of {B} patches"
     avg_s = ms / 1e3 / max(cnt, 1)
@@ -340,7 +346,7 @@ def main():
         if tg:
             ttt = {"target": tg["target"], "oracle_epochs": tg["epochs"],
                    "oracle_misfit_at_epochs": tg["final"]}
-            for path in [best, "plain"]:
+            for path in [best] + (["plain"] if "plain" in paths else []):
                 rec, obj, probe = fresh(path, *((bv, bf) if path == best else (0, 0)))
                 sec, ep, last, phi_at = time_to_target(rec, obj, probe, tg["target"],
                                                        3 * tg["epochs"], tg["epochs"])
@@ -370,7 +376,7 @@ def main():
                    "parallelism": "single GPU"},
         "paths": paths,
         "autotuned": tuned,
-        "fused_speedup_vs_plain": paths["plain"]["ms_per_epoch"] / t_best,
+        "fused_speedup_vs_plain": (paths["plain"]["ms_per_epoch"] / t_best) if "plain" in paths else None,
         "epoch_algorithmic_bytes": A_epoch,
         "epoch_hbm_roofline_frac": A_epoch / (t_best / 1e3) / 1e9 / HBM_PEAK_GBS,
         "time_to_target": ttt,

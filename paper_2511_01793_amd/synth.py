@@ -165,6 +165,9 @@ CONFIGS = {
     "c3": dict(n=1024, m=128, scan=("fermat", 10000), photons=1e7, B=256, L=3, alpha=0.05, epochs=20, idx=3),
     # differentiation: 256^2 object, 64^2 probe, 20x20 raster step 10, noiseless
     "c4": dict(n=256, m=64, scan=("raster", 20, 10, 0), photons=None, B=400, L=1, alpha=0.05, epochs=0, idx=4),
+    # 256^2 patterns (the crop size of the paper's beamline data): 31 x 31 raster, step 24,
+    # jitter 2, over a 1024^2 object, 1e8 photons, minibatch 32, 2 levels
+    "c6": dict(n=1024, m=256, scan=("raster", 31, 24, 2), photons=1e8, B=32, L=2, alpha=0.05, epochs=0, idx=6),
 }
 
 
