@@ -487,10 +487,7 @@ struct PersistFin {
 };
 
 struct FinLds {
-  int2 spos[kMaxSlots];
-  int list[kMaxSlots];
-  int nlist;
-  float2 pm[1024];
+  float2 pm[1024];  // probe partial sums of the slot groups
   float pe[1024];
 };
 
@@ -501,11 +498,6 @@ __host__ __device__ inline int finalize_items(int n, int G, int* ntiles_out) {
   const int ppu = FNT / G;
   *ntiles_out = tpr * tpr;
   return tpr * tpr + (M * M + ppu - 1) / ppu;
-}
-
-template <int M, int FNT>
-__device__ __forceinline__ void load_slot_positions(const StepArgs& a, FinLds& L, int tid) {
-  for (int s = tid; s < a.b; s += FNT) L.spos[s] = make_int2(a.slot[s].y, a.slot[s].z);
 }
 
 template <int M, int FNT, int T>
@@ -525,48 +517,45 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
       const int y = ty + q / T, x = tx + q % T;
       zold[e] = (a.joint && y < n && x < n) ? ld(a.obj, (size_t)y * n + x) : cx<float>{0.f, 0.f};
     }
-    // wave 0 lists the overlapping slots in ascending order
-    if (tid < 64) {
-      int cnt = 0;
-      for (int s0 = 0; s0 < a.b; s0 += 64) {
-        const int s = s0 + tid;
-        bool ov = false;
-        if (s < a.b) {
-          const int2 p = L.spos[s];
-          ov = !(p.x >= ty + T || p.x + M <= ty || p.y >= tx + T || p.y + M <= tx);
-        }
-        const unsigned long long mask = __ballot(ov);
-        if (ov) L.list[cnt + __popcll(mask & ((1ull << tid) - 1ull))] = s;
-        cnt += __popcll(mask);
-      }
-      if (tid == 0) L.nlist = cnt;
-    }
-    __syncthreads();
-    const int cnt = L.nlist;
-    if (cnt > 0) {
-      cx<float> accn[PER];
-      float accd[PER];
+    // Each wave scans the slots itself, 64 at a time: a ballot marks the ones whose
+    // window overlaps the tile, and the set bits are taken in ascending order, U per
+    // round (every load of a round is issued before its adds).  No list in LDS, no
+    // barrier; the order of the additions is ascending slot order.
+    cx<float> accn[PER];
+    float accd[PER];
 #pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        accn[e] = cx<float>{0.f, 0.f};
-        accd[e] = 0.f;
+    for (int e = 0; e < PER; ++e) {
+      accn[e] = cx<float>{0.f, 0.f};
+      accd[e] = 0.f;
+    }
+    constexpr int U = FNT >= 1024 ? 2 : 4;
+    const int lane = tid & 63;
+    for (int s0 = 0; s0 < a.b; s0 += 64) {
+      int px = 0, py = 0;
+      bool ov = false;
+      if (s0 + lane < a.b) {
+        const int4 sl = a.slot[s0 + lane];
+        px = sl.y;
+        py = sl.z;
+        ov = !(px >= ty + T || px + M <= ty || py >= tx + T || py + M <= tx);
       }
-      // U slots per round: every load of the round is issued before any add
-      constexpr int U = FNT >= 1024 ? 2 : 4;
-      for (int i0 = 0; i0 < cnt; i0 += U) {
+      unsigned long long mask = __ballot(ov);
+      while (mask) {
         cx<float> vn[U][PER];
         float vd[U][PER];
+        bool val[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int i = i0 + u;
-          const int s = i < cnt ? L.list[i] : 0;
-          const int2 p = L.spos[s];
-          const float2* ns = a.numer + (size_t)s * M * M;
+          val[u] = mask != 0ull;
+          const int bit = val[u] ? __builtin_ctzll(mask) : 0;
+          if (val[u]) mask &= mask - 1ull;
+          const int ox = __builtin_amdgcn_readlane(px, bit), oy = __builtin_amdgcn_readlane(py, bit);
+          const float2* ns = a.numer + (size_t)(s0 + bit) * M * M;
 #pragma unroll
           for (int e = 0; e < PER; ++e) {
             const int q = tid + e * FNT;
-            const int ry = ty + q / T - p.x, rx = tx + q % T - p.y;
-            const bool in = i < cnt && (unsigned)ry < (unsigned)M && (unsigned)rx < (unsigned)M;
+            const int ry = ty + q / T - ox, rx = tx + q % T - oy;
+            const bool in = val[u] && (unsigned)ry < (unsigned)M && (unsigned)rx < (unsigned)M;
             vn[u][e] = in ? ld(ns, ry * M + rx) : cx<float>{0.f, 0.f};
             vd[u][e] = in ? a.Dbuf[ry * M + rx] : 0.f;
           }
@@ -575,25 +564,24 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
         for (int u = 0; u < U; ++u) {
 #pragma unroll
           for (int e = 0; e < PER; ++e) {
-            if (i0 + u < cnt) {
+            if (val[u]) {
               accn[e] = add(accn[e], vn[u][e]);
               accd[e] += vd[u][e];
             }
           }
         }
       }
+    }
 #pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int q = tid + e * FNT;
-        const int y = ty + q / T, x = tx + q % T;
-        if (accd[e] > 0.f && y < n && x < n) {
-          const size_t o = (size_t)y * n + x;
-          const cx<float> zp = scale(accn[e], 1.f / accd[e]);
-          st(a.obj, o, a.joint ? aligned_sqrt(zold[e], zp) : zp);
-        }
+    for (int e = 0; e < PER; ++e) {
+      const int q = tid + e * FNT;
+      const int y = ty + q / T, x = tx + q % T;
+      if (accd[e] > 0.f && y < n && x < n) {
+        const size_t o = (size_t)y * n + x;
+        const cx<float> zp = scale(accn[e], 1.f / accd[e]);
+        st(a.obj, o, a.joint ? aligned_sqrt(zold[e], zp) : zp);
       }
     }
-    __syncthreads();  // the slot list is rewritten by the next tile
   } else {
     // probe unit: ppu pixels x G slot groups; group g sums slots [g per, (g + 1) per)
     // in ascending order, then the G partials are added in group order
@@ -699,8 +687,6 @@ __global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize(StepArgs a, int n
   constexpr int FNT = FinShape<F>::FNT, T = FinShape<F>::T;
   __shared__ FinLds L;
   const int tid = threadIdx.x;
-  load_slot_positions<M, FNT>(a, L, tid);
-  __syncthreads();
   finalize_item<M, FNT, T>(a, blockIdx.x, ntiles, L, tid);
 }
 
@@ -714,8 +700,6 @@ __global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize_multi(const StepA
   const StepArgs a = args[w.x];
   int ntiles;
   finalize_items<M, FNT, T>(a.n, a.pgroups, &ntiles);
-  load_slot_positions<M, FNT>(a, L, tid);
-  __syncthreads();
   finalize_item<M, FNT, T>(a, w.y, ntiles, L, tid);
 }
 
@@ -770,8 +754,6 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_epoch_persistent(StepArgs 
       patch_step<M, V, L>(x, s, A, tws, redf, redd, tid);
     target += gridDim.x;
     grid_barrier(bar, target, err);
-    load_slot_positions<M, NT>(x, FL, tid);
-    __syncthreads();
     for (int item = blockIdx.x; item < nitems; item += gridDim.x)
       finalize_item<M, NT, FT>(x, item, ntiles, FL, tid);
     target += gridDim.x;
