@@ -133,6 +133,11 @@ __device__ __forceinline__ cx<float> ld(const float2* p, size_t i) {
   float2 v = p[i];
   return cx<float>{v.x, v.y};
 }
+// 32-bit element offset: the load takes the base in scalar registers
+__device__ __forceinline__ cx<float> ld32(const float2* p, unsigned i) {
+  float2 v = p[i];
+  return cx<float>{v.x, v.y};
+}
 __device__ __forceinline__ void st(float2* p, size_t i, cx<float> v) { p[i] = make_float2(v.re, v.im); }
 // two consecutive complex values at an even index of a 16-byte aligned array
 __device__ __forceinline__ void ld_pair(const float2* p, size_t i, cx<float>& a, cx<float>& b) {
@@ -386,14 +391,18 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
   cx<float> qc[P::CACHE ? 4 : 1], zc[P::CACHE ? 4 : 1];
   float amp[CP::PTS];
   float q2m = 0.f, z2m = 0.f;
+  auto load_amps = [&]() {
 #pragma unroll
-  for (int it = 0; it < CP::IT; ++it) {
-    const int w = tid + it * CP::NT;
-    if (CP::ITEMS < CP::NT && w >= CP::ITEMS) break;
-    const int line = w % M, g = w / M;
+    for (int it = 0; it < CP::IT; ++it) {
+      const int w = tid + it * CP::NT;
+      if (CP::ITEMS < CP::NT && w >= CP::ITEMS) break;
+      const int line = w % M, g = w / M;
 #pragma unroll
-    for (int j = 0; j < CP::R1; ++j) amp[it * CP::R1 + j] = dk[(CP::R1 * g + j) * M + line];
-  }
+      for (int j = 0; j < CP::R1; ++j) amp[it * CP::R1 + j] = dk[(CP::R1 * g + j) * M + line];
+    }
+  };
+  constexpr int AS = Plan<M, V>::AMP;
+  if constexpr (AS == 0) load_amps();
 #pragma unroll
   for (int rd = 0; rd < R; ++rd) {
     int r0, c0;
@@ -420,7 +429,16 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
   // before they are read in the per-pixel phase
   wave_max2_to_lds<NT>(q2m, z2m, redf, tid);
   __syncthreads();
-  fft2_forward_head<float, M, V>(A, tws, tid);
+  // the forward transform's first three passes (rows, rows, columns)
+  fft_pass<float, M, V, false, true, false>(A, tws, tid);
+  __syncthreads();
+  if constexpr (AS == 1) load_amps();
+  fft_pass<float, M, V, false, false, false>(A, tws, tid);
+  __syncthreads();
+  if constexpr (AS == 2) load_amps();
+  fft_pass<float, M, V, false, true, true>(A, tws, tid);
+  __syncthreads();
+  if constexpr (AS == 3) load_amps();
   // last forward pass, modulus projection, first inverse pass, in registers
   double acc = 0.0;
   float2* ph = a.phase ? a.phase + (size_t)k * M * M : nullptr;
@@ -500,6 +518,24 @@ __host__ __device__ inline int finalize_items(int n, int G, int* ntiles_out) {
   return tpr * tpr + (M * M + ppu - 1) / ppu;
 }
 
+// an empty register barrier: v is taken as written here, so later uses do not
+// wait on the load that produced it
+__device__ __forceinline__ void settle(int4& v) {
+  asm volatile("" : "+v"(v.y), "+v"(v.z));
+}
+
+// the lowest set bit of a wave-uniform ballot mask: that lane's slot and window origin
+__device__ __forceinline__ bool take_slot(unsigned long long& m, const int4& v, int base, int& slot,
+                                          int& ox, int& oy) {
+  if (m == 0ull) return false;
+  const int bit = __builtin_ctzll(m);
+  m &= m - 1ull;
+  slot = base + bit;
+  ox = __builtin_amdgcn_readlane(v.y, bit);
+  oy = __builtin_amdgcn_readlane(v.z, bit);
+  return true;
+}
+
 template <int M, int FNT, int T>
 __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int ntiles, FinLds& L,
                                               int tid) {
@@ -517,10 +553,11 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
       const int y = ty + q / T, x = tx + q % T;
       zold[e] = (a.joint && y < n && x < n) ? ld(a.obj, (size_t)y * n + x) : cx<float>{0.f, 0.f};
     }
-    // Each wave scans the slots itself, 64 at a time: a ballot marks the ones whose
-    // window overlaps the tile, and the set bits are taken in ascending order, U per
-    // round (every load of a round is issued before its adds).  No list in LDS, no
-    // barrier; the order of the additions is ascending slot order.
+    // Each wave scans the slots itself, 256 at a time (four loads of 64 issued
+    // together): a ballot per 64 marks the ones whose window overlaps the tile, and
+    // the set bits are taken in ascending order, U per round (every load of a round
+    // is issued before its adds; a round may span the four ballots).  No list in LDS,
+    // no barrier; the order of the additions is ascending slot order.
     cx<float> accn[PER];
     float accd[PER];
 #pragma unroll
@@ -530,44 +567,64 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
     }
     constexpr int U = FNT >= 1024 ? 2 : 4;
     const int lane = tid & 63;
-    for (int s0 = 0; s0 < a.b; s0 += 64) {
-      int px = 0, py = 0;
-      bool ov = false;
-      if (s0 + lane < a.b) {
-        const int4 sl = a.slot[s0 + lane];
-        px = sl.y;
-        py = sl.z;
-        ov = !(px >= ty + T || px + M <= ty || py >= tx + T || py + M <= tx);
-      }
-      unsigned long long mask = __ballot(ov);
-      while (mask) {
+    for (int s0 = 0; s0 < a.b; s0 += 256) {
+      int4 sl0{0, 0, 0, 0}, sl1{0, 0, 0, 0}, sl2{0, 0, 0, 0}, sl3{0, 0, 0, 0};
+      const int s = s0 + lane;
+      if (s < a.b) sl0 = a.slot[s];
+      if (s + 64 < a.b) sl1 = a.slot[s + 64];
+      if (s + 128 < a.b) sl2 = a.slot[s + 128];
+      if (s + 192 < a.b) sl3 = a.slot[s + 192];
+      // the positions are settled here, once: without this the compiler waits for
+      // every outstanding load before each lane read of them in the rounds below
+      settle(sl0);
+      settle(sl1);
+      settle(sl2);
+      settle(sl3);
+      auto overlaps = [&](const int4& v, int j) {
+        return j < a.b && !(v.y >= ty + T || v.y + M <= ty || v.z >= tx + T || v.z + M <= tx);
+      };
+      unsigned long long m0 = __ballot(overlaps(sl0, s)), m1 = __ballot(overlaps(sl1, s + 64)),
+                         m2 = __ballot(overlaps(sl2, s + 128)), m3 = __ballot(overlaps(sl3, s + 192));
+      // next overlapping slot in ascending order (the masks are wave-uniform)
+      auto pop = [&](int& slot, int& ox, int& oy) -> bool {
+        return take_slot(m0, sl0, s0, slot, ox, oy) || take_slot(m1, sl1, s0 + 64, slot, ox, oy) ||
+               take_slot(m2, sl2, s0 + 128, slot, ox, oy) || take_slot(m3, sl3, s0 + 192, slot, ox, oy);
+      };
+      while ((m0 | m1 | m2 | m3) != 0ull) {
         cx<float> vn[U][PER];
         float vd[U][PER];
-        bool val[U];
+        int sidx[U], ox[U], oy[U];
+        // the round's slots first (lane reads of the positions), then its loads: a
+        // lane read placed after a load would wait for that load.  cnt (wave-uniform)
+        // slots are live; the loops stop there.
+        int cnt = 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          val[u] = mask != 0ull;
-          const int bit = val[u] ? __builtin_ctzll(mask) : 0;
-          if (val[u]) mask &= mask - 1ull;
-          const int ox = __builtin_amdgcn_readlane(px, bit), oy = __builtin_amdgcn_readlane(py, bit);
-          const float2* ns = a.numer + (size_t)(s0 + bit) * M * M;
+          if (!pop(sidx[u], ox[u], oy[u])) break;
+          ++cnt;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (u >= cnt) break;
+          // 32-bit offsets (b m^2 < 2^31): one base address for every load
+          const int sb = sidx[u] * (M * M);
 #pragma unroll
           for (int e = 0; e < PER; ++e) {
             const int q = tid + e * FNT;
-            const int ry = ty + q / T - ox, rx = tx + q % T - oy;
-            const bool in = val[u] && (unsigned)ry < (unsigned)M && (unsigned)rx < (unsigned)M;
-            vn[u][e] = in ? ld(ns, ry * M + rx) : cx<float>{0.f, 0.f};
-            vd[u][e] = in ? a.Dbuf[ry * M + rx] : 0.f;
+            const int ry = ty + q / T - ox[u], rx = tx + q % T - oy[u];
+            const bool in = (unsigned)ry < (unsigned)M && (unsigned)rx < (unsigned)M;
+            vn[u][e] = in ? ld32(a.numer, (unsigned)(sb + ry * M + rx)) : cx<float>{0.f, 0.f};
+            vd[u][e] = in ? a.Dbuf[(unsigned)(ry * M + rx)] : 0.f;
           }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+          if (u >= cnt) break;
 #pragma unroll
           for (int e = 0; e < PER; ++e) {
-            if (val[u]) {
-              accn[e] = add(accn[e], vn[u][e]);
-              accd[e] += vd[u][e];
-            }
+            accn[e] = add(accn[e], vn[u][e]);
+            accd[e] += vd[u][e];
           }
         }
       }
@@ -632,10 +689,22 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
         st(a.probe, r, a.joint ? aligned_sqrt(qold, qp) : qp);
       }
     }
-    if (item == ntiles && tid == 0 && a.sampled) {
+    // the batch's sampled misfit: lane j sums the slots j, j + 64, ... (four loads
+    // in flight), then the wave sum in its fixed order
+    if (item == ntiles && tid < 64 && a.sampled) {
       double t = 0.0;
-      for (int s = 0; s < a.b; ++s) t += a.phi[s];
-      *a.sampled += t;
+      for (int s0 = 0; s0 < a.b; s0 += 256) {
+        double v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = s0 + 64 * c + tid;
+          v[c] = j < a.b ? a.phi[j] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) t += v[c];
+      }
+      t = wave_sum(t);
+      if (tid == 0) *a.sampled += t;
     }
     __syncthreads();
   }
