@@ -499,7 +499,28 @@ emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* i
       P.fin_us[f] = 1000.f * ms;
       if (P.fin_us[f] < P.fin_us[best]) best = f;
     }
-    c->cfg.finalize_shape = best;
+    // The two fastest shapes alone can rank the other way inside an epoch (the
+    // finalize leaves the caches to the next patch stage): the fused epoch decides.
+    static_assert(emg::kFinShapes >= 2, "two finalize shapes to compare");
+    int second = best == 0 ? 1 : 0;
+    for (int f = 0; f < emg::kFinShapes; ++f)
+      if (f != best && P.fin_us[f] < P.fin_us[second]) second = f;
+    const int saved_path = c->cfg.path;
+    c->cfg.path = EMAGPIE_PATH_FUSED;
+    float ep[2] = {0.f, 0.f};
+    const int pair[2] = {best, second};
+    int64_t epoch = 0;
+    for (int i = 0; i < 2; ++i) {
+      c->cfg.finalize_shape = pair[i];
+      EMG_OK(time_kernel(s, 1, 3, [&](int, hipEvent_t e0, hipEvent_t e1) -> emagpie_status {
+        if (e0) EMG_HIP(hipEventRecord(e0, s));
+        EMG_OK(emagpie_epoch(c, tobj, tprobe, epoch++, nullptr, nullptr, s));
+        if (e1) EMG_HIP(hipEventRecord(e1, s));
+        return EMAGPIE_OK;
+      }, &ep[i]));
+    }
+    c->cfg.path = saved_path;
+    c->cfg.finalize_shape = ep[1] < ep[0] ? second : best;
   }
   // 3. path: whole epochs on the scratch state
   if (req.path == EMAGPIE_PATH_AUTO) {
