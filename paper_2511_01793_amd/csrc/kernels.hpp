@@ -372,12 +372,19 @@ __device__ __forceinline__ float project_px(cx<float>& P, float dval, float2* ph
 // the whole patch stage for slot s, LDS-resident
 // ---------------------------------------------------------------------------
 // Returns the slot's sampled misfit (in thread 0).
-template <int M, int V, int L, bool DIRECT = false>
+// STAGE: the twiddle table is loaded here (its load goes out beside the slot's,
+// its LDS copy is written before the first barrier) instead of by the caller.
+template <int M, int V, int L, bool DIRECT = false, bool STAGE = false>
 __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>* A,
-                                           const cx<float>* tws, float* redf, double* redd,
+                                           cx<float>* tws, float* redf, double* redd,
                                            int tid) {
   using P = Px<M, V>;
   constexpr int R = P::ROUNDS, NT = P::NT, LS = P::LS;
+  static_assert(M <= NT, "one twiddle per thread");
+  cx<float> twv{0.f, 0.f};
+  if constexpr (STAGE) {
+    if (tid < M) twv = ld(a.tw, tid);
+  }
   const int4 sl = a.slot[s];
   const int k = sl.x;
   const size_t n = (size_t)a.n;
@@ -402,7 +409,6 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
     }
   };
   constexpr int AS = Plan<M, V>::AMP;
-  if constexpr (AS == 0) load_amps();
 #pragma unroll
   for (int rd = 0; rd < R; ++rd) {
     int r0, c0;
@@ -414,6 +420,10 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
       zz[2 * i] = ld(zwin, (size_t)(r0 + i) * n + c0);
       zz[2 * i + 1] = ld(zwin, (size_t)(r0 + i) * n + c0 + 1);
     }
+    // the intensities go out behind the first exit-wave loads, which are needed first
+    if constexpr (AS == 0) {
+      if (rd == 0) load_amps();
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       if constexpr (P::CACHE) {
@@ -424,6 +434,9 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
       z2m = fmaxf(z2m, norm2(zz[e]));
       A[(r0 + (e >> 1)) * LS + c0 + (e & 1)] = mul(q[e], zz[e]);
     }
+  }
+  if constexpr (STAGE) {
+    if (tid < M) tws[tid] = twv;
   }
   // wave maxima go to LDS now; the barriers of the transforms order them
   // before they are read in the per-pixel phase
@@ -725,9 +738,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step(StepArgs a) {
   __shared__ float redf[32];
   __shared__ double redd[16];
   const int tid = threadIdx.x;
-  stage_twiddles<M, Plan<M, V>::NT>(a.tw, tws, tid);
-  __syncthreads();
-  patch_step<M, V, L>(a, blockIdx.x, A, tws, redf, redd, tid);
+  patch_step<M, V, L, false, true>(a, blockIdx.x, A, tws, redf, redd, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -746,9 +757,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step_multi(const Ste
   const int tid = threadIdx.x;
   const int2 w = work[blockIdx.x];
   const StepArgs a = args[w.x];
-  stage_twiddles<M, Plan<M, V>::NT>(a.tw, tws, tid);
-  __syncthreads();
-  patch_step<M, V, L>(a, w.y, A, tws, redf, redd, tid);
+  patch_step<M, V, L, false, true>(a, w.y, A, tws, redf, redd, tid);
 }
 
 template <int M, int F>
