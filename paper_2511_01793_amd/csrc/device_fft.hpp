@@ -232,19 +232,11 @@ __device__ __forceinline__ void fft2_forward(cx<T>* A, const cx<T>* tw, int tid)
   __syncthreads();
 }
 
-// The forward transform without its last pass, and the inverse without its
-// first.  The last forward pass and the first inverse pass are the same
-// contiguous column pass (same items per thread, no twiddles), so a caller can
-// run both in registers with per-element work between them (fft_pass_pair).
-template <typename T, int M, int V>
-__device__ __forceinline__ void fft2_forward_head(cx<T>* A, const cx<T>* tw, int tid) {
-  fft_pass<T, M, V, false, true, false>(A, tw, tid);
-  __syncthreads();
-  fft_pass<T, M, V, false, false, false>(A, tw, tid);
-  __syncthreads();
-  fft_pass<T, M, V, false, true, true>(A, tw, tid);
-  __syncthreads();
-}
+// The inverse transform without its first pass.  The last forward pass and the
+// first inverse pass are the same contiguous column pass (same items per thread,
+// no twiddles), so a caller runs the forward transform's first three passes, then
+// both of these in registers with per-element work between them (fft_pass_pair),
+// then this tail.
 template <typename T, int M, int V>
 __device__ __forceinline__ void fft2_inverse_tail(cx<T>* A, const cx<T>* tw, int tid) {
   fft_pass<T, M, V, true, true, true>(A, tw, tid);
