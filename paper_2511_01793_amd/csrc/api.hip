@@ -55,6 +55,28 @@ void fisher_yates(uint64_t seed, int64_t epoch, int32_t n, int32_t* out) {
   }
 }
 
+// Listing order of one minibatch's slots for the launch.  Workgroup i of a launch
+// runs on XCD i mod X (X accelerator complex dies, each with its own L2), so the
+// slots are sorted by window corner (row, then column) and the sorted run is dealt
+// in X contiguous parts: part x goes to slots x, x + X, x + 2X, ...  Neighbouring
+// windows then share an L2 and re-read each other's object pixels from it.  The
+// minibatch is a set (every sum over it runs in listing order, the same on every
+// launch strategy), so this changes rounding order only.  Left as it is unless
+// X > 1 divides b and b >= 2X.
+void xcd_listing(int4* d, int b, int xcc, std::vector<int4>& tmp) {
+  if (xcc <= 1 || b < 2 * xcc || b % xcc != 0) return;
+  tmp.assign(d, d + b);
+  std::stable_sort(tmp.begin(), tmp.end(), [](const int4& p, const int4& q) {
+    return p.y != q.y ? p.y < q.y : p.z < q.z;
+  });
+  const int per = b / xcc;
+  for (int x = 0; x < xcc; ++x)
+    for (int k = 0; k < per; ++k) d[x + xcc * k] = tmp[x * per + k];
+}
+void xcd_listing_sweep(int4* d, int n, int B, int xcc, std::vector<int4>& tmp) {
+  for (int s0 = 0; s0 < n; s0 += B) xcd_listing(d + s0, std::min(B, n - s0), xcc, tmp);
+}
+
 struct Region {
   size_t off, bytes;
 };
@@ -168,6 +190,8 @@ struct emagpie_ctx_s {
   std::vector<int32_t> perm_host;
   double dp_avg = 0.0;
   int num_cus = 0;
+  int num_xcc = 1;  // accelerator complex dies (each with its own L2)
+  std::vector<int4> listing_tmp;
   int persist_grid = 0;
   unsigned* bar = nullptr;  // persistent-kernel barrier counter (grows monotonically)
   unsigned bar_base = 0;
@@ -454,6 +478,7 @@ emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* i
     const int k = perm[j];
     pin[j] = make_int4(k, c->pos_host[2 * k], c->pos_host[2 * k + 1], 0);
   }
+  xcd_listing_sweep(pin, N, std::min(B, N), c->num_xcc, c->listing_tmp);
   EMG_HIP(hipMemcpyAsync(c->slots, pin, sizeof(int4) * N, hipMemcpyHostToDevice, s));
   EMG_HIP(hipStreamSynchronize(s));
   const int b = std::min(B, N), nb = std::max(1, N / b);
@@ -640,6 +665,9 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   if ((e = hipGetDevice(&dev)) != hipSuccess) return hipfail(e, "hipGetDevice");
   if ((e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return hipfail(e, "hipDeviceGetAttribute");
+  if (hipDeviceGetAttribute(&ctx->num_xcc, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess ||
+      ctx->num_xcc < 1)
+    ctx->num_xcc = 1;
   // the plan the context starts with: the configured one, or the defaults
   // until the autotuner below has chosen
   if (ctx->cfg.fft_plan == EMAGPIE_TUNE) ctx->cfg.fft_plan = 0;
@@ -842,6 +870,7 @@ emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, in
       const int k = ctx->perm_host[j];
       dst[j] = make_int4(k, ctx->pos_host[2 * k], ctx->pos_host[2 * k + 1], 0);
     }
+    xcd_listing_sweep(dst, N, std::min(ctx->cfg.minibatch, N), ctx->num_xcc, ctx->listing_tmp);
     EMG_HIP(hipMemcpyAsync(ctx->slots, dst, sizeof(int4) * N, hipMemcpyHostToDevice, s));
     EMG_HIP(hipEventRecord(ctx->perm_ev[slot], s));
   }
@@ -1248,6 +1277,7 @@ emagpie_status emagpie_group_epoch(emagpie_group g, void* const* obj_devs, void*
       const int k = g->perm_host[j];
       d[j] = make_int4(k, c->pos_host[2 * k], c->pos_host[2 * k + 1], 0);
     }
+    xcd_listing_sweep(d, N, std::min(c->cfg.minibatch, N), c->num_xcc, c->listing_tmp);
     total += N;
   }
   EMG_HIP(hipMemcpyAsync(g->slots_dev, dst, total * sizeof(int4), hipMemcpyHostToDevice, s));

@@ -1,5 +1,7 @@
 """Minibatch sizes that are not multiples of the finalize's slot scan (64 slots per ballot,
-256 per step) and ragged last minibatches, in every finalize shape, against the oracle."""
+256 per step) and ragged last minibatches, in every finalize shape, against the oracle; and
+minibatches whose slots the epoch lists in XCD order (B a multiple of the XCD count), where
+every launch strategy must still agree bit for bit."""
 import numpy as np
 import pytest
 
@@ -41,10 +43,11 @@ def epoch_from(pos, d, n, m, B, L, shape, seed, state):
     return obj, probe, float(s.item())
 
 
-@pytest.mark.parametrize("B, N", [(300, 650), (257, 520), (130, 400)])
+@pytest.mark.parametrize("B, N", [(300, 650), (257, 520), (130, 400), (256, 600)])
 def test_ragged_minibatches_every_shape(B, N):
     # B = 300: ballots of 64, 64, 64, 64 and 44 over two scan steps; last batch of 50.
     # B = 257: one slot past a scan step; last batch of 6.  B = 130: a ragged third ballot.
+    # B = 256: full scan steps, listed in XCD order, and a last batch of 88 (also listed).
     n, m, L = 160, 32, 2
     pos, d = scattered(n, m, N, seed=B)
     rng = np.random.default_rng(B + 1)
@@ -62,3 +65,36 @@ def test_ragged_minibatches_every_shape(B, N):
     assert rel(host(runs[0][0]), z1) < EPOCH_TOL, rel(host(runs[0][0]), z1)
     assert rel(host(runs[0][1]), q1) < EPOCH_TOL, rel(host(runs[0][1]), q1)
     assert abs(runs[0][2] - samp) <= MISFIT_TOL * samp
+
+
+def test_xcd_listing_every_path_bitwise():
+    # B = 32 (a multiple of 8): the epoch lists each minibatch's slots in XCD order; plain,
+    # fused, graph and persistent launches of the same sweep agree bit for bit, and with the
+    # oracle (which sums in its own order) to the epoch bar
+    n, m, L, B, N = 160, 32, 2, 32, 200
+    pos, d = scattered(n, m, N, seed=77)
+    rng = np.random.default_rng(78)
+    z0 = (0.9 + 0.1 * rng.random((n, n))) * np.exp(0.3j * rng.standard_normal((n, n)))
+    q0 = synth.initial_probe(m).astype(np.complex128) * np.sqrt(d.sum(axis=(1, 2)).mean()) / m
+    say("case: xcd listing, every path")
+    out = {}
+    for path in ("plain", "fused", "graph", "persistent"):
+        rec = E.Reconstruction(pos, torch.from_numpy(d).cuda(), n, minibatch=B, levels=L,
+                               alpha=0.05, path=path, seed=5)
+        obj = torch.from_numpy(z0.astype(np.complex64)).cuda()
+        probe = torch.from_numpy(q0.astype(np.complex64)).cuda()
+        s = torch.zeros((), dtype=torch.float64, device="cuda")
+        rec.epoch(obj, probe, 3, sampled=s)
+        torch.cuda.synchronize()
+        out[path] = (obj, probe, float(s.item()))
+        rec.close()
+    for path in ("fused", "graph", "persistent"):
+        assert torch.equal(out[path][0], out["plain"][0]), path
+        assert torch.equal(out[path][1], out["plain"][1]), path
+        assert out[path][2] == out["plain"][2], path
+    q, z, samp = O.run_epoch(q0.astype(np.complex64).astype(np.complex128),
+                             z0.astype(np.complex64).astype(np.complex128), pos, O.amplitudes(d),
+                             seed=5, epoch=3, minibatch=B, alpha=0.05, levels=L)
+    assert rel(host(out["fused"][0]), z) < EPOCH_TOL, rel(host(out["fused"][0]), z)
+    assert rel(host(out["fused"][1]), q) < EPOCH_TOL, rel(host(out["fused"][1]), q)
+    assert abs(out["fused"][2] - samp) <= MISFIT_TOL * samp
