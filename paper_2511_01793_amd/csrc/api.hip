@@ -319,12 +319,13 @@ void fill_plan_info(emagpie_ctx c, int tuned) {
   p.fft_plan = c->cfg.fft_plan;
   emg::fft_plan_desc(c->cfg.m, p.fft_plan, &p.r1, &p.r2, &p.threads);
   p.finalize_shape = c->cfg.finalize_shape;
-  emg::fin_shape_desc(p.finalize_shape, &p.fin_threads, &p.fin_tile);
+  emg::fin_shape_desc(p.finalize_shape, &p.fin_threads, &p.fin_tile, &p.fin_banded);
   p.path = c->cfg.path;
   p.tuned = tuned;
   if (tuned == 0) {
     p.n_fft_plans = p.n_fin_shapes = 0;
-    for (int i = 0; i < 4; ++i) p.fft_us[i] = p.fin_us[i] = -1.f;
+    for (float& x : p.fft_us) x = -1.f;
+    for (float& x : p.fin_us) x = -1.f;
     for (float& x : p.path_ms) x = -1.f;
   }
 }
@@ -400,7 +401,7 @@ void cache_append(const char* path, const std::string& key, const emagpie_plan& 
                "{\"key\": \"%s\", \"fft_plan\": %d, \"finalize_shape\": %d, \"path\": %d, "
                "\"fft_us\": %s, \"fin_us\": %s, \"path_ms\": %s}\n",
                key.c_str(), p.fft_plan, p.finalize_shape, p.path, arr(p.fft_us, 4).c_str(),
-               arr(p.fin_us, 4).c_str(), arr(p.path_ms, 6).c_str());
+               arr(p.fin_us, emg::kFinShapes).c_str(), arr(p.path_ms, 6).c_str());
   std::fclose(fp);
 }
 
@@ -527,6 +528,7 @@ emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* i
     // The two fastest shapes alone can rank the other way inside an epoch (the
     // finalize leaves the caches to the next patch stage): the fused epoch decides.
     static_assert(emg::kFinShapes >= 2, "two finalize shapes to compare");
+    static_assert(sizeof(P.fin_us) / sizeof(P.fin_us[0]) >= emg::kFinShapes, "room for every shape");
     int second = best == 0 ? 1 : 0;
     for (int f = 0; f < emg::kFinShapes; ++f)
       if (f != best && P.fin_us[f] < P.fin_us[second]) second = f;
@@ -758,7 +760,7 @@ emagpie_status emagpie_plan_describe(int32_t m, int32_t fft_plan, int32_t finali
   emagpie_plan p{};
   if (!emg::fft_plan_desc(m, fft_plan, &p.r1, &p.r2, &p.threads))
     return fail(EMAGPIE_E_ARG, "no such FFT plan for this m");
-  if (!emg::fin_shape_desc(finalize_shape, &p.fin_threads, &p.fin_tile))
+  if (!emg::fin_shape_desc(finalize_shape, &p.fin_threads, &p.fin_tile, &p.fin_banded))
     return fail(EMAGPIE_E_ARG, "no such finalize shape");
   p.fft_plan = fft_plan;
   p.finalize_shape = finalize_shape;

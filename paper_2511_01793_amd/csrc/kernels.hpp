@@ -765,7 +765,13 @@ __global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize(StepArgs a, int n
   constexpr int FNT = FinShape<F>::FNT, T = FinShape<F>::T;
   __shared__ FinLds L;
   const int tid = threadIdx.x;
-  finalize_item<M, FNT, T>(a, blockIdx.x, ntiles, L, tid);
+  int item = blockIdx.x;
+  if constexpr (FinShape<F>::BANDED) {
+    // block i (on XCD i mod X) takes tile (i mod X) * ntiles / X + i / X
+    constexpr int X = kDispatchXcds;
+    if (item < ntiles && ntiles % X == 0) item = (item % X) * (ntiles / X) + item / X;
+  }
+  finalize_item<M, FNT, T>(a, item, ntiles, L, tid);
 }
 
 template <int M, int F>
@@ -1206,6 +1212,10 @@ hipError_t with_fin(int f, Fn&& fn) {
     case 1: return fn(IC<1>{});
     case 2: return fn(IC<2>{});
     case 3: return fn(IC<3>{});
+    case 4: return fn(IC<4>{});
+    case 5: return fn(IC<5>{});
+    case 6: return fn(IC<6>{});
+    case 7: return fn(IC<7>{});
     default: return hipErrorInvalidValue;
   }
 }

@@ -16,8 +16,9 @@
 // values are not held through the passes before (they would be spilled).
 //
 // Finalize shape (variant): FNT threads per work item, object tiles of
-// T x T pixels.  Every shape sums the same terms in the same order, so the
-// results are bitwise identical; only the speed differs.
+// T x T pixels, and the order the blocks take the tiles in.  Every shape sums
+// the same terms in the same order, so the results are bitwise identical; only
+// the speed differs.
 #pragma once
 
 namespace emg {
@@ -63,19 +64,31 @@ inline bool fft_plan_desc(int m, int v, int* r1, int* r2, int* nt) {
 }
 inline int fft_plan_count(int m) { return m == 32 ? 2 : m == 64 ? 4 : m == 128 ? 3 : m == 256 ? 1 : 0; }
 
-// finalize shapes: (threads per item, object tile side)
-template <int F> struct FinShape;
-template <> struct FinShape<0> { static constexpr int FNT = 256, T = 32; };
-template <> struct FinShape<1> { static constexpr int FNT = 256, T = 16; };
-template <> struct FinShape<2> { static constexpr int FNT = 512, T = 32; };
-template <> struct FinShape<3> { static constexpr int FNT = 1024, T = 64; };
-constexpr int kFinShapes = 4;
+// finalize shapes: (threads per item, object tile side) for F & 3, and the
+// order in which the grid's blocks take the object tiles for F >> 2: row-major
+// (0) or banded (1).  Block i of a launch runs on XCD i mod kDispatchXcds; banded,
+// XCD x takes the x-th contiguous band of tile rows, the band of the object whose
+// patches the same XCD ran when the minibatch was listed for the XCDs, so their
+// numerators may still be in its L2.  Which order is faster depends on how the
+// scan spreads the work (uniform rasters favour bands, a dense centre favours
+// row-major), so both are candidates for the autotuner.
+constexpr int kDispatchXcds = 8;
+template <int F> struct FinShapeBase;
+template <> struct FinShapeBase<0> { static constexpr int FNT = 256, T = 32; };
+template <> struct FinShapeBase<1> { static constexpr int FNT = 256, T = 16; };
+template <> struct FinShapeBase<2> { static constexpr int FNT = 512, T = 32; };
+template <> struct FinShapeBase<3> { static constexpr int FNT = 1024, T = 64; };
+template <int F> struct FinShape : FinShapeBase<F & 3> {
+  static constexpr bool BANDED = ((F >> 2) & 1) != 0;
+};
+constexpr int kFinShapes = 8;
 
-inline bool fin_shape_desc(int f, int* fnt, int* tile) {
-  static const int t[kFinShapes][2] = {{256, 32}, {256, 16}, {512, 32}, {1024, 64}};
+inline bool fin_shape_desc(int f, int* fnt, int* tile, int* banded = nullptr) {
+  static const int t[4][2] = {{256, 32}, {256, 16}, {512, 32}, {1024, 64}};
   if (f < 0 || f >= kFinShapes) return false;
-  *fnt = t[f][0];
-  *tile = t[f][1];
+  *fnt = t[f & 3][0];
+  *tile = t[f & 3][1];
+  if (banded) *banded = (f >> 2) & 1;
   return true;
 }
 
