@@ -767,9 +767,13 @@ __global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize(StepArgs a, int n
   const int tid = threadIdx.x;
   int item = blockIdx.x;
   if constexpr (FinShape<F>::BANDED) {
-    // block i (on XCD i mod X) takes tile (i mod X) * ntiles / X + i / X
+    // Blocks i < ntiles with i mod X = x are the k-th (k = i / X) of the q + (x < r)
+    // blocks on XCD x (ntiles = q X + r); they take band x, tiles x q + min(x, r) + k.
     constexpr int X = kDispatchXcds;
-    if (item < ntiles && ntiles % X == 0) item = (item % X) * (ntiles / X) + item / X;
+    if (item < ntiles) {
+      const int q = ntiles / X, r = ntiles % X, x = item % X;
+      item = x * q + min(x, r) + item / X;
+    }
   }
   finalize_item<M, FNT, T>(a, item, ntiles, L, tid);
 }
