@@ -213,18 +213,40 @@ struct PxLayout {
   __device__ static void origin(int tid, int rd, int& r0, int& c0) { blk_origin<M, V>(tid, rd, r0, c0); }
 };
 
-template <int M, class LY, int L, bool DIRECT, class LOAD>
+// PF: the next round's values are loaded before this round's arithmetic, so
+// their latency hides behind it (one round of values more in registers).
+template <int M, class LY, int L, bool DIRECT, class LOAD, bool PF = false>
 __device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int tid, int row0,
                                                 LOAD load, float qqmax, float zmax) {
   const size_t base = (size_t)s * M * M;
   const bool slot_den = a.pden_slot != nullptr;
+  cx<float> qn[4], zn[4], Rn[4];
+  if constexpr (PF) {
+    int r0, c0;
+    LY::origin(tid, 0, r0, c0);
+    load(0, r0 + row0, c0, qn, zn, Rn);
+  }
 #pragma unroll
   for (int rd = 0; rd < LY::ROUNDS; ++rd) {
     int r0, c0;
     LY::origin(tid, rd, r0, c0);
     r0 += row0;
     cx<float> q[4], zz[4], R[4];
-    load(rd, r0, c0, q, zz, R);
+    if constexpr (PF) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        q[e] = qn[e];
+        zz[e] = zn[e];
+        R[e] = Rn[e];
+      }
+      if (rd + 1 < LY::ROUNDS) {
+        int r1, c1;
+        LY::origin(tid, rd + 1, r1, c1);
+        load(rd + 1, r1 + row0, c1, qn, zn, Rn);
+      }
+    } else {
+      load(rd, r0, c0, q, zz, R);
+    }
     // per pixel: |Q|^2, u, D = |Q|^2 + u, conj(Q) R (shared by the coarse-grid residual
     // g = conj(Q)(R - Q z) = conj(Q) R - |Q|^2 z and the object numerator)
     float q2[4], u[4], D[4];
@@ -320,7 +342,8 @@ __device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int ti
 template <int M, int V, int L, bool DIRECT = false, class LOAD>
 __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, LOAD load,
                                              float qqmax, float zmax) {
-  pixel_update_ly<M, PxLayout<M, V>, L, DIRECT>(a, s, tid, 0, load, qqmax, zmax);
+  pixel_update_ly<M, PxLayout<M, V>, L, DIRECT, LOAD, (Plan<M, V>::PF != 0)>(a, s, tid, 0, load,
+                                                                            qqmax, zmax);
 }
 
 // modulus projection of one pixel in transform order: Psi' = a Psi/|Psi|

@@ -10,6 +10,9 @@
 // another split reorders the DFT arithmetic (same transform, other rounding)
 // and lays the intensities out in its own transform order.
 //
+// PF = 1: the per-pixel phase loads each round's values one round ahead (a gain
+// for the two-round 512-thread plan at m = 64; at m = 128 the extra registers
+// cost more than the hidden latency).
 // AMP is where the patch kernel issues the loads of the measured intensities:
 // 0 with the exit-wave loads at the start, k > 0 after the k-th forward pass.
 // Plans whose registers are tight at 1024 threads issue them late, so the
@@ -24,17 +27,17 @@
 namespace emg {
 
 template <int M, int V> struct Plan;
-template <> struct Plan<32, 0> { static constexpr int R1 = 8, R2 = 4, NT = 256; static constexpr int AMP = 0; };
-template <> struct Plan<32, 1> { static constexpr int R1 = 4, R2 = 8, NT = 256; static constexpr int AMP = 0; };
-template <> struct Plan<64, 0> { static constexpr int R1 = 8, R2 = 8, NT = 1024; static constexpr int AMP = 0; };
-template <> struct Plan<64, 1> { static constexpr int R1 = 16, R2 = 4, NT = 1024; static constexpr int AMP = 2; };
-template <> struct Plan<64, 2> { static constexpr int R1 = 4, R2 = 16, NT = 1024; static constexpr int AMP = 0; };
-template <> struct Plan<64, 3> { static constexpr int R1 = 8, R2 = 8, NT = 512; static constexpr int AMP = 0; };
-template <> struct Plan<128, 0> { static constexpr int R1 = 16, R2 = 8, NT = 1024; static constexpr int AMP = 3; };
-template <> struct Plan<128, 1> { static constexpr int R1 = 8, R2 = 16, NT = 1024; static constexpr int AMP = 2; };
-template <> struct Plan<128, 2> { static constexpr int R1 = 16, R2 = 8, NT = 512; static constexpr int AMP = 0; };
+template <> struct Plan<32, 0> { static constexpr int R1 = 8, R2 = 4, NT = 256; static constexpr int AMP = 0, PF = 0; };
+template <> struct Plan<32, 1> { static constexpr int R1 = 4, R2 = 8, NT = 256; static constexpr int AMP = 0, PF = 0; };
+template <> struct Plan<64, 0> { static constexpr int R1 = 8, R2 = 8, NT = 1024; static constexpr int AMP = 0, PF = 0; };
+template <> struct Plan<64, 1> { static constexpr int R1 = 16, R2 = 4, NT = 1024; static constexpr int AMP = 2, PF = 0; };
+template <> struct Plan<64, 2> { static constexpr int R1 = 4, R2 = 16, NT = 1024; static constexpr int AMP = 0, PF = 0; };
+template <> struct Plan<64, 3> { static constexpr int R1 = 8, R2 = 8, NT = 512; static constexpr int AMP = 0, PF = 1; };
+template <> struct Plan<128, 0> { static constexpr int R1 = 16, R2 = 8, NT = 1024; static constexpr int AMP = 3, PF = 0; };
+template <> struct Plan<128, 1> { static constexpr int R1 = 8, R2 = 16, NT = 1024; static constexpr int AMP = 2, PF = 0; };
+template <> struct Plan<128, 2> { static constexpr int R1 = 16, R2 = 8, NT = 512; static constexpr int AMP = 0, PF = 0; };
 // m = 256: the tile exceeds LDS; strips of 16 lines per workgroup (see kernels256.hpp)
-template <> struct Plan<256, 0> { static constexpr int R1 = 16, R2 = 16, NT = 256; static constexpr int AMP = 0; };
+template <> struct Plan<256, 0> { static constexpr int R1 = 16, R2 = 16, NT = 256; static constexpr int AMP = 0, PF = 0; };
 
 template <int M> struct PlanCount;
 template <> struct PlanCount<32> { static constexpr int value = 2; };
