@@ -243,8 +243,8 @@ def main():
                          "instances) or c6 (256^2 patterns, 961 positions, minibatch 32)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); how the path would shard "
+              "over several GPUs is a design, not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
