@@ -179,7 +179,13 @@ emagpie_status emagpie_step_minibatch(emagpie_ctx ctx, void* obj_dev, void* prob
  * Fisher-Yates shuffle driven by SplitMix64 (see emagpie_permutation).  If
  * sampled_misfit_dev is not null it is overwritten with the sum of the
  * sampled misfits of the sweep.  The path in the config selects the launch
- * strategy; results do not depend on it.
+ * strategy; results do not depend on it.  In the library's own order each
+ * minibatch is listed for the device's XCDs before its slots are summed:
+ * sorted by window corner and dealt in one contiguous part per XCD (when the
+ * XCD count divides the minibatch and it has at least two slots per XCD), so
+ * the rounding order of the sums, and with it the last bits, can differ
+ * between devices with different XCD counts.  A caller's perm_dev is used as
+ * given.
  */
 emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, int64_t epoch,
                              const int32_t* perm_dev, double* sampled_misfit_dev, void* stream);
