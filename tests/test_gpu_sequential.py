@@ -54,6 +54,18 @@ def test_chain_path_equals_fused_path_bitwise(m, L):
     assert sf == sc
 
 
+@pytest.mark.parametrize("m, v", [(64, 3), (64, 1), (128, 2)])
+def test_chain_path_equals_fused_path_bitwise_other_plans(m, v):
+    # plans with two or more per-pixel rounds (64 / 3 loads each round's values one round
+    # ahead, beside the in-place writes of the minibatch-1 update)
+    p = small(m, 2)
+    say("case: chain plan", m, v)
+    of, qf, sf = sweep(p, path="fused", fft_plan=v)
+    oc, qc, sc = sweep(p, path="chain", fft_plan=v)
+    assert torch.equal(of, oc) and torch.equal(qf, qc)
+    assert sf == sc
+
+
 def test_chain_path_epoch_parity_with_the_oracle():
     p = small(32, 2)
     say("case: chain vs oracle")
