@@ -51,6 +51,40 @@ def test_group_epochs_equal_individual_epochs_bitwise():
         r.close()
 
 
+def test_group_with_xcd_listed_minibatches_equals_individual_bitwise():
+    # minibatches of 16, 24 and 32 slots (multiples of 8): each member's epoch lists them for
+    # the XCDs, alone and in the group alike
+    import paper_2511_01793_amd.emagpie as E
+    specs = [
+        dict(n=160, m=32, scan=("raster", 8, 16, 1), photons=1e6, B=16, L=2, seed=41),
+        dict(n=200, m=64, scan=("raster", 7, 22, 1), photons=1e6, B=24, L=3, seed=42),
+        dict(n=150, m=32, scan=("raster", 9, 14, 1), photons=None, B=32, L=1, seed=43),
+    ]
+    ps = [problem("tiny", alpha=0.05, **sp) for sp in specs]
+    print("case: group vs individual, listed minibatches", flush=True)
+    solo = []
+    for i, p in enumerate(ps):
+        rec = make_rec(p, path="fused", seed=300 + i)
+        obj, probe = init_state(p, rec)
+        for e in range(2):
+            rec.epoch(obj, probe, e)
+        torch.cuda.synchronize()
+        solo.append((obj.cpu().numpy(), probe.cpu().numpy()))
+        rec.close()
+    recs = [make_rec(p, path="fused", seed=300 + i) for i, p in enumerate(ps)]
+    states = [init_state(p, r) for p, r in zip(ps, recs)]
+    grp = E.Group(recs)
+    for e in range(2):
+        grp.epoch([o for o, _ in states], [q for _, q in states], e)
+    torch.cuda.synchronize()
+    for i, ((o, q), ref) in enumerate(zip(states, solo)):
+        assert np.array_equal(o.cpu().numpy(), ref[0]), i
+        assert np.array_equal(q.cpu().numpy(), ref[1]), i
+    grp.close()
+    for r in recs:
+        r.close()
+
+
 def test_group_member_matches_oracle_epoch():
     import paper_2511_01793_amd.emagpie as E
     ps = members()[:3]
