@@ -33,6 +33,11 @@ struct StripLayout {
 };
 }  // namespace big
 
+// Every kernel below runs (slot, strip) pairs strip-major: block i takes slot
+// i mod b and strip i / b, so with b a multiple of the XCD count all strips of a
+// slot run on one XCD (block i runs on XCD i mod 8), beside the slots listed next
+// to it, and the overlapping windows' object rows meet in that XCD's L2.
+//
 // 1. psi and forward row passes of strip rb of slot s (or of pattern k0 + s when
 // a.slot is null: the misfit over all patterns)
 __global__ __launch_bounds__(256) void k256_rows_fwd(StepArgs a, int k0) {
@@ -40,7 +45,8 @@ __global__ __launch_bounds__(256) void k256_rows_fwd(StepArgs a, int k0) {
   __shared__ cx<float> A[S * LSR];
   __shared__ cx<float> tws[M];
   __shared__ float redf[2 * NT / 64];
-  const int tid = threadIdx.x, s = blockIdx.x / S, rb = blockIdx.x % S, row0 = rb * S;
+  const int tid = threadIdx.x, nsl = gridDim.x / S, s = blockIdx.x % nsl, rb = blockIdx.x / nsl,
+            row0 = rb * S;
   int wr, wc;
   if (a.slot) {
     const int4 sl = a.slot[s];
@@ -87,7 +93,8 @@ __global__ __launch_bounds__(256) void k256_cols(StepArgs a, int k0) {
   __shared__ cx<float> A[M * LSC];
   __shared__ cx<float> tws[M];
   __shared__ double redd[NT / 64];
-  const int tid = threadIdx.x, s = blockIdx.x / S, cb = blockIdx.x % S, col0 = cb * S;
+  const int tid = threadIdx.x, nsl = gridDim.x / S, s = blockIdx.x % nsl, cb = blockIdx.x / nsl,
+            col0 = cb * S;
   const int k = a.slot ? a.slot[s].x : k0 + s;
   // the pair pass has S * R2 = NT items of R1 points: item tid, line tid % S,
   // positions R1 (tid / S) + j; its amplitudes are loaded first
@@ -138,7 +145,8 @@ __global__ __launch_bounds__(256) void k256_rows_inv(StepArgs a) {
   using namespace big;
   __shared__ cx<float> A[S * LSR];
   __shared__ cx<float> tws[M];
-  const int tid = threadIdx.x, s = blockIdx.x / S, rb = blockIdx.x % S, row0 = rb * S;
+  const int tid = threadIdx.x, nsl = gridDim.x / S, s = blockIdx.x % nsl, rb = blockIdx.x / nsl,
+            row0 = rb * S;
   const int4 sl = a.slot[s];
   tws[tid] = ld(a.tw, tid);
   const float2* in = a.stack + (size_t)s * M * M + (size_t)row0 * M;
