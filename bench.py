@@ -226,6 +226,64 @@ def bench_group(K, W):
             "epoch_hbm_roofline_frac": A / t_grp / 1e9 / HBM_PEAK_GBS}
 
 
+def bench_grad(K, W):
+    """The differentiation workload (256^2 object, 64^2 probe, 20 x 20 raster = 400 positions):
+    full misfit Phi (Eq. 1) and its hand-written adjoint gradient, float32 and float64, each
+    timed over K calls after W warm-up calls (all inputs resident on the device)."""
+    import torch
+    import paper_2511_01793_amd.emagpie as E
+    from paper_2511_01793_amd import synth
+    log("building workload c4 ...")
+    p = synth.make_problem("c4")
+    n, m, N = p.n, p.m, p.n_pos
+    d = torch.from_numpy(p.intensities).cuda()
+    rec = E.Reconstruction(p.positions, d, n, minibatch=p.minibatch, levels=p.levels,
+                           alpha=p.alpha, path="fused", seed=p.seed)
+    obj = torch.from_numpy(p.object_init).cuda()
+    probe = torch.from_numpy(p.probe_init).cuda()
+    rec.normalize_probe(probe)
+    rec.epoch(obj, probe, 0)  # a mid-reconstruction state
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        for _ in range(W):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / K
+
+    o64, q64 = obj.to(torch.complex128), probe.to(torch.complex128)
+    t_mis = timed(lambda: rec.misfit(obj, probe))
+    t_g32 = timed(lambda: rec.grad(obj, probe))
+    t_g64 = timed(lambda: rec.grad(o64, q64))
+    rec.close()
+    # algorithmic bytes: amplitudes (4 B/px) and window gather (8 B/px) per pattern, probe
+    # read; the gradient also writes the object gradient (n^2) and the probe gradient (m^2)
+    a_mis = N * m * m * 12 + 8 * m * m
+    a_g32 = a_mis + 8 * n * n + 8 * m * m
+    a_g64 = N * m * m * (4 + 16) + 16 * m * m + 16 * n * n + 16 * m * m
+    log(f"misfit      {t_mis * 1e6:9.1f} us   ({a_mis / t_mis / 1e9:7.1f} GB/s)")
+    log(f"grad f32    {t_g32 * 1e6:9.1f} us   ({a_g32 / t_g32 / 1e9:7.1f} GB/s)")
+    log(f"grad f64    {t_g64 * 1e6:9.1f} us   ({a_g64 / t_g64 / 1e9:7.1f} GB/s)")
+    return {"metric": "gradient evaluations/s (Phi and its adjoint, whole scan)", "value": 1.0 / t_g32,
+            "unit": "evaluations/s", "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": t_g32 * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "256^2 object, 64^2 probe, 20x20 raster (400 positions), "
+                                   "noiseless", "n": n, "m": m, "positions": N},
+            "misfit_us": t_mis * 1e6, "grad_f32_us": t_g32 * 1e6, "grad_f64_us": t_g64 * 1e6,
+            "roofline": {"bound": "hbm", "achieved": a_g32 / t_g32 / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": a_g32 / t_g32 / 1e9 / HBM_PEAK_GBS,
+                         "traffic": None, "kernel": "emagpie_grad (f32, whole call)",
+                         "algorithmic_bytes_per_launch": a_g32,
+                         "launch_unit": "one gradient of the whole scan"},
+            "misfit_hbm_frac": a_mis / t_mis / 1e9 / HBM_PEAK_GBS,
+            "grad_f64_hbm_frac": a_g64 / t_g64 / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,9 +295,10 @@ def main():
                     help="fix the FFT plan, finalize shape and path of the tuned leg instead of "
                          "autotuning (e.g. 3,1,fused; for profiler runs, whose timing distorts "
                          "the autotuner)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5", "c6"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c6"],
                     help="c2 (default, the headline workload), c3 (1024^2 object, 128^2 probe, "
-                         "10000-point Fermat spiral, minibatch 256, 3 levels), c5 (16 uneven "
+                         "10000-point Fermat spiral, minibatch 256, 3 levels), c4 (misfit and "
+                         "adjoint gradient, 256^2 object, 400 positions), c5 (16 uneven "
                          "instances) or c6 (256^2 patterns, 961 positions, minibatch 32)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -255,6 +314,9 @@ def main():
     K, W = args.steps, args.warmup
     if args.workload == "c5":
         print(json.dumps(bench_group(K, W)))
+        return
+    if args.workload == "c4":
+        print(json.dumps(bench_grad(K, W)))
         return
     log(f"building workload {args.workload} ...")
     p = synth.make_problem(args.workload)

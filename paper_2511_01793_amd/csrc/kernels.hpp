@@ -1115,47 +1115,106 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_grad_patch(GradArgs g, int
   if (tid == 0) g.phi_all[k] = tot / (2.0 * M * M);
 }
 
+// Deterministic reductions of the per-pattern gradient slots.  Both split a
+// chunk's patterns into contiguous groups summed in parallel (ascending order
+// inside a group) and add the group partials in group order, with several loads
+// in flight per round; the order depends only on the chunk, not on the launch.
+constexpr int kGradTile = 16;   // object gradient tiles kGradTile^2
+constexpr int kGradZGroups = 4; // pattern groups per object tile (one per 256 threads)
+constexpr int kGradQGroups = 16;  // pattern groups per probe pixel
+
+__device__ __forceinline__ void settle2(int2& v) {
+  asm volatile("" : "+v"(v.x), "+v"(v.y));
+}
+
+// object gradient: tile of kGradTile^2 pixels, kGradZGroups x 256 threads
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_grad_scatter(GradArgs g, int k0, int cnt, int first) {
-  __shared__ int2 spos[kMaxSlots];
-  constexpr int TS = 32, PER = 4;
-  const int tid = threadIdx.x, n = g.n;
-  for (int s = tid; s < cnt; s += 256) spos[s] = g.pos[k0 + s];
-  __syncthreads();
+__global__ __launch_bounds__(256 * kGradZGroups) void k_grad_scatter(GradArgs g, int k0, int cnt,
+                                                                      int first) {
+  constexpr int TS = kGradTile, GS = kGradZGroups, U = 8;
+  static_assert(TS * TS == 256, "one pixel per thread of a group");
+  __shared__ cx<T> part[(GS - 1) * TS * TS];
+  const int tid = threadIdx.x, gi = tid >> 8, q = tid & 255, lane = tid & 63, n = g.n;
   const int tpr = (n + TS - 1) / TS;
   const int ty = (blockIdx.x / tpr) * TS, tx = (blockIdx.x % tpr) * TS;
-  cx<T> acc[PER];
+  const int y = ty + q / TS, x = tx + q % TS;
+  const int per = (cnt + GS - 1) / GS, lo = min(cnt, gi * per), hi = min(cnt, lo + per);
+  cx<T> acc{T(0), T(0)};
+  for (int s0 = lo; s0 < hi; s0 += 64) {
+    const int sj = s0 + lane;
+    int2 p{0, 0};
+    if (sj < hi) p = g.pos[k0 + sj];
+    settle2(p);
+    const bool ov = sj < hi && !(p.x >= ty + TS || p.x + M <= ty || p.y >= tx + TS || p.y + M <= tx);
+    unsigned long long m = __ballot(ov);
+    while (m != 0ull) {
+      int sl[U], ox[U], oy[U];
+      int c = 0;
 #pragma unroll
-  for (int e = 0; e < PER; ++e) acc[e] = cx<T>{T(0), T(0)};
-  for (int s = 0; s < cnt; ++s) {
-    const int2 p = spos[s];
-    if (p.x >= ty + TS || p.x + M <= ty || p.y >= tx + TS || p.y + M <= tx) continue;
+      for (int u = 0; u < U; ++u) {
+        if (m == 0ull) break;
+        const int bit = __builtin_ctzll(m);
+        m &= m - 1ull;
+        sl[u] = s0 + bit;
+        ox[u] = __builtin_amdgcn_readlane(p.x, bit);
+        oy[u] = __builtin_amdgcn_readlane(p.y, bit);
+        ++c;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      cx<T> v[U];
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int q = tid + e * 256;
-      const int ry = ty + q / TS - p.x, rx = tx + q % TS - p.y;
-      if ((unsigned)ry < (unsigned)M && (unsigned)rx < (unsigned)M)
-        acc[e] = add(acc[e], ldT<T>(g.gz_slots, (size_t)s * M * M + ry * M + rx));
+      for (int u = 0; u < U; ++u) {
+        if (u >= c) break;
+        const int ry = y - ox[u], rx = x - oy[u];
+        const bool in = (unsigned)ry < (unsigned)M && (unsigned)rx < (unsigned)M;
+        v[u] = in ? ldT<T>(g.gz_slots, (size_t)sl[u] * M * M + ry * M + rx) : cx<T>{T(0), T(0)};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (u >= c) break;
+        acc = add(acc, v[u]);
+      }
     }
   }
+  if (gi > 0) part[(gi - 1) * TS * TS + q] = acc;
+  __syncthreads();
+  if (gi == 0 && y < n && x < n) {
 #pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    const int q = tid + e * 256;
-    const int y = ty + q / TS, x = tx + q % TS;
-    if (y < n && x < n) {
-      const size_t o = (size_t)y * n + x;
-      stT<T>(g.gobj, o, first ? acc[e] : add(ldT<T>(g.gobj, o), acc[e]));
-    }
+    for (int k = 1; k < GS; ++k) acc = add(acc, part[(k - 1) * TS * TS + q]);
+    const size_t o = (size_t)y * n + x;
+    stT<T>(g.gobj, o, first ? acc : add(ldT<T>(g.gobj, o), acc));
   }
 }
 
+// probe gradient: 256 / kGradQGroups pixels x kGradQGroups pattern groups per block
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_grad_probe(GradArgs g, int cnt, int first) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= M * M) return;
+  constexpr int G = kGradQGroups, PPU = 256 / G, U = 8;
+  __shared__ cx<T> part[256];
+  const int tid = threadIdx.x, gi = tid / PPU, lp = tid % PPU;
+  const int r = blockIdx.x * PPU + lp;
+  const bool live = r < M * M;
+  const int per = (cnt + G - 1) / G, lo = min(cnt, gi * per), hi = min(cnt, lo + per);
   cx<T> acc{T(0), T(0)};
-  for (int s = 0; s < cnt; ++s) acc = add(acc, ldT<T>(g.gq_slots, (size_t)s * M * M + r));
-  stT<T>(g.gprobe, r, first ? acc : add(ldT<T>(g.gprobe, r), acc));
+  if (live) {
+    for (int s0 = lo; s0 < hi; s0 += U) {
+      cx<T> v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        v[u] = s0 + u < hi ? ldT<T>(g.gq_slots, (size_t)(s0 + u) * M * M + r) : cx<T>{T(0), T(0)};
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (s0 + u < hi) acc = add(acc, v[u]);
+    }
+  }
+  part[tid] = acc;
+  __syncthreads();
+  if (gi == 0 && live) {
+    cx<T> t = part[lp];
+#pragma unroll
+    for (int k = 1; k < G; ++k) t = add(t, part[lp + k * PPU]);
+    stT<T>(g.gprobe, r, first ? t : add(ldT<T>(g.gprobe, r), t));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1449,15 +1508,16 @@ hipError_t Launchers<M>::chain(int v, int L, const StepArgs& a, int n_steps, hip
 
 template <typename T, int M, int V>
 static hipError_t grad_t(const GradArgs& g, hipStream_t s) {
-  constexpr int NT = Plan<M, V>::NT, TS = 32;
+  constexpr int NT = Plan<M, V>::NT, TS = kGradTile, PPU = 256 / kGradQGroups;
   const int tpr = (g.n + TS - 1) / TS;
   for (int k0 = 0; k0 < g.n_pos; k0 += g.chunk) {
     const int cnt = min(g.chunk, g.n_pos - k0);
     const int first = k0 == 0;
     hipLaunchKernelGGL((k_grad_patch<T, M, V>), dim3(cnt), dim3(NT), 0, s, g, k0);
-    hipLaunchKernelGGL((k_grad_scatter<T, M>), dim3(tpr * tpr), dim3(256), 0, s, g, k0, cnt, first);
-    hipLaunchKernelGGL((k_grad_probe<T, M>), dim3((M * M + 255) / 256), dim3(256), 0, s, g, cnt,
-                       first);
+    hipLaunchKernelGGL((k_grad_scatter<T, M>), dim3(tpr * tpr), dim3(256 * kGradZGroups), 0, s, g,
+                       k0, cnt, first);
+    hipLaunchKernelGGL((k_grad_probe<T, M>), dim3((M * M + PPU - 1) / PPU), dim3(256), 0, s, g,
+                       cnt, first);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
