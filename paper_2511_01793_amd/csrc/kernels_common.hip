@@ -11,8 +11,17 @@ extern template struct Launchers<128>;
 
 __global__ __launch_bounds__(256) void k_sum_doubles(const double* in, int count, double* out) {
   __shared__ double redd[16];
+  // thread t adds in[t], in[t + 256], ... in that order; eight loads in flight per round
+  constexpr int U = 8;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < count; i += 256) acc += in[i];
+  for (int i0 = threadIdx.x; i0 < count; i0 += 256 * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = i0 + 256 * u < count ? in[i0 + 256 * u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + 256 * u < count) acc += v[u];
+  }
   const double tot = block_sum<256>(acc, redd, threadIdx.x);
   if (threadIdx.x == 0) out[0] = tot;
 }
