@@ -1080,26 +1080,39 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_grad_patch(GradArgs g, int
     pix_rc<M, V>(tid, e, r, c);
     A[r * LS + c] = mul(ldT<T>(g.probe, (size_t)r * M + c), ldT<T>(g.obj, (pk.x + r) * n + pk.y + c));
   }
-  __syncthreads();
-  fft2_forward<T, M, V>(A, tws, tid);
-  // residual in Fourier space: Psi - Psi' = (|Psi| - a) Psi/|Psi|, or -a where Psi = 0
+  // the intensities in the order the middle pass visits them (see patch_step)
+  using CP = ColPass<M, V>;
   const float* dk = g.dperm + (size_t)k * M * M;
+  float dv[CP::PTS];
+#pragma unroll
+  for (int it = 0; it < CP::IT; ++it) {
+    const int w = tid + it * CP::NT;
+    if (CP::ITEMS < CP::NT && w >= CP::ITEMS) break;
+    const int line = w % M, gg = w / M;
+#pragma unroll
+    for (int j = 0; j < CP::R1; ++j) dv[it * CP::R1 + j] = dk[(CP::R1 * gg + j) * M + line];
+  }
+  __syncthreads();
+  fft_pass<T, M, V, false, true, false>(A, tws, tid);
+  __syncthreads();
+  fft_pass<T, M, V, false, false, false>(A, tws, tid);
+  __syncthreads();
+  fft_pass<T, M, V, false, true, true>(A, tws, tid);
+  __syncthreads();
+  // last forward pass, residual in Fourier space, first inverse pass, in registers:
+  // Psi - Psi' = (|Psi| - a) Psi/|Psi|, or -a where Psi = 0
   const T inv_m2 = T(1) / T(M * M);
   double acc = 0.0;
-#pragma unroll
-  for (int e = 0; e < PX; ++e) {
-    int r, c;
-    pix_rc<M, V>(tid, e, r, c);
-    const cx<T> P = A[r * LS + c];
-    const T amp = sqrt(fmax(T(dk[r * M + c]), T(0)));
+  fft_pass_pair<T, M, V>(A, tid, [&](int e, cx<T>& P) {
+    const T amp = sqrt(fmax(T(dv[e]), T(0)));
     const T mag = sqrt(norm2(P));
     const T diff = mag - amp;
     acc += (double)diff * (double)diff;
     const cx<T> E = mag > T(0) ? scale(P, diff / mag) : cx<T>{-amp, T(0)};
-    A[r * LS + c] = scale(E, inv_m2);
-  }
+    P = scale(E, inv_m2);
+  });
   __syncthreads();
-  fft2_inverse<T, M, V>(A, tws, tid);
+  fft2_inverse_tail<T, M, V>(A, tws, tid);
   const size_t base = (size_t)s * M * M;
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
