@@ -260,6 +260,26 @@ struct ColPass {
 // Last forward pass, f(item point, value) on each transformed value, first
 // inverse pass: in registers, one LDS read and one write per point.  Caller
 // synchronises before (the head's barrier) and after.
+// Last forward pass in registers: each transformed value goes to f(item point,
+// value) and is not written back (for consumers that only reduce it).
+template <typename T, int M, int V, class F>
+__device__ __forceinline__ void fft_pass_last(const cx<T>* A, int tid, F f) {
+  using C = ColPass<M, V>;
+  constexpr int LS = lds_stride<M>();
+#pragma unroll
+  for (int it = 0; it < C::IT; ++it) {
+    const int w = tid + it * C::NT;
+    if (C::ITEMS < C::NT && w >= C::ITEMS) break;
+    const int line = w % M, g = w / M;
+    cx<T> v[C::R1];
+#pragma unroll
+    for (int j = 0; j < C::R1; ++j) v[j] = A[(C::R1 * g + j) * LS + line];
+    dft_small<T, false, C::R1, M>(v, nullptr);
+#pragma unroll
+    for (int j = 0; j < C::R1; ++j) f(it * C::R1 + j, v[j]);
+  }
+}
+
 template <typename T, int M, int V, class F>
 __device__ __forceinline__ void fft_pass_pair(cx<T>* A, int tid, F f) {
   using C = ColPass<M, V>;

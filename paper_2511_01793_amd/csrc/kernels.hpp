@@ -1010,23 +1010,35 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, 
   const int2 pk = slot ? make_int2(slot[blockIdx.x].y, slot[blockIdx.x].z) : pos[k];
   const float* dk = dperm + (size_t)k * M * M;
   stage_twiddles<M, NT>(tw, tws, tid);
-  float dv[PX];
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
     int r, c;
     pix_rc<M, V>(tid, e, r, c);
-    dv[e] = dk[r * M + c];
     A[r * LS + c] = mul(ld(probe, (size_t)r * M + c), ld(obj, (size_t)(pk.x + r) * n + pk.y + c));
   }
-  __syncthreads();
-  fft2_forward<float, M, V>(A, tws, tid);
-  double acc = 0.0;
+  // the intensities in the order the last pass visits them
+  using CP = ColPass<M, V>;
+  float dv[CP::PTS];
 #pragma unroll
-  for (int e = 0; e < PX; ++e) {
-    int r, c;
-    pix_rc<M, V>(tid, e, r, c);
-    acc += (double)project_px<M>(A[r * LS + c], dv[e]);
+  for (int it = 0; it < CP::IT; ++it) {
+    const int w = tid + it * CP::NT;
+    if (CP::ITEMS < CP::NT && w >= CP::ITEMS) break;
+    const int line = w % M, g = w / M;
+#pragma unroll
+    for (int j = 0; j < CP::R1; ++j) dv[it * CP::R1 + j] = dk[(CP::R1 * g + j) * M + line];
   }
+  __syncthreads();
+  fft_pass<float, M, V, false, true, false>(A, tws, tid);
+  __syncthreads();
+  fft_pass<float, M, V, false, false, false>(A, tws, tid);
+  __syncthreads();
+  fft_pass<float, M, V, false, true, true>(A, tws, tid);
+  __syncthreads();
+  // the last pass hands each transformed value to the misfit term, in registers
+  double acc = 0.0;
+  fft_pass_last<float, M, V>(A, tid, [&](int e, cx<float> P) {
+    acc += (double)project_px<M>(P, dv[e]);
+  });
   const double tot = block_sum<NT>(acc, redd, tid);
   if (tid == 0) phi_all[blockIdx.x] = tot / (2.0 * M * M);
 }
