@@ -45,7 +45,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("device_fft.hpp", "plans.hpp", "kernels.hpp", "launch.hpp")
+KERNEL_SOURCES = ("device_fft.hpp", "plans.hpp", "kernels.hpp", "launch.hpp", "build.py")
 
 
 def kernel_source_digest():

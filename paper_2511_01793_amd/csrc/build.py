@@ -22,10 +22,13 @@ SOURCES = ["kernels_m32.hip", "kernels_m64.hip", "kernels_m128.hip", "kernels_m2
 # and says so; that message is harmless.  Floating-point contraction is off so
 # that every operation is rounded on its own: the same source arithmetic then
 # gives the same bits in every kernel that inlines it (all launch strategies
-# agree bitwise).
+# agree bitwise).  Up to six leading kernel arguments are preloaded into scalar
+# registers at dispatch (the patch and finalize kernels put the pointers their
+# first loads need there).
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-kernarg-preload-count=6",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

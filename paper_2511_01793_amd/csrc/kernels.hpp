@@ -754,8 +754,20 @@ __device__ __forceinline__ void stage_twiddles(const float2* tw, cx<float>* tws,
   for (int j = tid; j < M; j += NT) tws[j] = ld(tw, j);
 }
 
+// k_patch_step and k_finalize take the slot list, the object and its side (and
+// the finalize the slot count) as leading arguments of their own, ahead of the
+// argument record, whose copies of them they replace.  The library is built
+// with kernel-argument preloading: leading scalar and pointer arguments arrive
+// in scalar registers at dispatch, so a kernel's first slot and object loads do
+// not wait for a load of its argument record (the record's fields are loaded
+// beside them).
 template <int M, int V, int L>
-__global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step(StepArgs a) {
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step(const int4* slot, float2* obj,
+                                                                 int n, StepArgs rec) {
+  StepArgs a = rec;
+  a.slot = slot;
+  a.obj = obj;
+  a.n = n;
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ float redf[32];
@@ -784,7 +796,13 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step_multi(const Ste
 }
 
 template <int M, int F>
-__global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize(StepArgs a, int ntiles) {
+__global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize(const int4* slot, float2* obj, int n,
+                                                               int b, StepArgs rec, int ntiles) {
+  StepArgs a = rec;
+  a.slot = slot;
+  a.obj = obj;
+  a.n = n;
+  a.b = b;
   constexpr int FNT = FinShape<F>::FNT, T = FinShape<F>::T;
   __shared__ FinLds L;
   const int tid = threadIdx.x;
@@ -1341,11 +1359,15 @@ hipError_t Launchers<M>::patch_step(int v, int L, const StepArgs& a, hipStream_t
       constexpr int V = decltype(vc)::value, LV = decltype(lc)::value, NT = Plan<M, V>::NT;
       if (e0) {
         StepArgs aa = a;
-        void* args[] = {&aa};
+        const int4* sl = a.slot;
+        float2* ob = a.obj;
+        int n = a.n;
+        void* args[] = {&sl, &ob, &n, &aa};
         return hipExtLaunchKernel((const void*)k_patch_step<M, V, LV>, dim3(a.b), dim3(NT), args,
                                   0, s, e0, e1, 0);
       }
-      hipLaunchKernelGGL((k_patch_step<M, V, LV>), dim3(a.b), dim3(NT), 0, s, a);
+      hipLaunchKernelGGL((k_patch_step<M, V, LV>), dim3(a.b), dim3(NT), 0, s, a.slot, a.obj, a.n,
+                         a);
       return hipGetLastError();
     });
   });
@@ -1360,11 +1382,15 @@ hipError_t Launchers<M>::finalize(int f, const StepArgs& a, hipStream_t s, hipEv
     const int items = finalize_items<M, FNT, T>(a.n, a.pgroups, &ntiles);
     if (e0) {
       StepArgs aa = a;
-      void* args[] = {&aa, &ntiles};
+      const int4* sl = a.slot;
+      float2* ob = a.obj;
+      int n = a.n, b = a.b;
+      void* args[] = {&sl, &ob, &n, &b, &aa, &ntiles};
       return hipExtLaunchKernel((const void*)k_finalize<M, F>, dim3(items), dim3(FNT), args, 0, s,
                                 e0, e1, 0);
     }
-    hipLaunchKernelGGL((k_finalize<M, F>), dim3(items), dim3(FNT), 0, s, a, ntiles);
+    hipLaunchKernelGGL((k_finalize<M, F>), dim3(items), dim3(FNT), 0, s, a.slot, a.obj, a.n, a.b,
+                       a, ntiles);
     return hipGetLastError();
   });
 }

@@ -239,11 +239,15 @@ hipError_t Launchers256::finalize(int f, const StepArgs& a, hipStream_t s, hipEv
     const int items = finalize_items<M, FNT, T>(a.n, a.pgroups, &ntiles);
     if (e0) {
       StepArgs aa = a;
-      void* args[] = {&aa, &ntiles};
+      const int4* sl = a.slot;
+      float2* ob = a.obj;
+      int n = a.n, b = a.b;
+      void* args[] = {&sl, &ob, &n, &b, &aa, &ntiles};
       return hipExtLaunchKernel((const void*)k_finalize<M, F>, dim3(items), dim3(FNT), args, 0, s,
                                 e0, e1, 0);
     }
-    hipLaunchKernelGGL((k_finalize<M, F>), dim3(items), dim3(FNT), 0, s, a, ntiles);
+    hipLaunchKernelGGL((k_finalize<M, F>), dim3(items), dim3(FNT), 0, s, a.slot, a.obj, a.n, a.b,
+                       a, ntiles);
     return hipGetLastError();
   });
 }
