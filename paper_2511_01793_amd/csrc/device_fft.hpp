@@ -301,6 +301,80 @@ __device__ __forceinline__ void fft_pass_pair(cx<T>* A, int tid, F f) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident passes for the split m = 8 * 8 with cross-lane transposes.
+// A line of 64 points (a row or a column of the tile) lives in the 8 lanes
+// base + 8 i (i = 0..7) of one wave, 8 points per lane.  For a strided pass lane
+// i holds points i + 8 j in register j: the pass's 8-point DFT and its twiddles
+// W^(i j) are lane-local.  An 8 x 8 transpose across the 8 lanes (lane bits
+// 3..5 exchanged with register bits 0..2) then leaves lane i holding points
+// 8 i + j, the run of the contiguous pass.  The DFTs, the twiddle products and
+// their operand order are those of fft_pass, so a tile transformed this way is
+// bitwise the tile the LDS passes of the same split give.
+// ---------------------------------------------------------------------------
+// Exchange between lanes l and l ^ D of a register pair (a, b): lanes with the
+// D bit clear take the partner's a into b, lanes with it set take the partner's
+// b into a.  D = 8: two DPP moves (row rotation by 8 within 16-lane rows, the
+// bank mask picking the receiving half); D = 16, 32: one lane-swap instruction.
+template <int D>
+__device__ __forceinline__ void xl_exchange(float& a, float& b) {
+  const int ia = __float_as_int(a), ib = __float_as_int(b);
+  if constexpr (D == 8) {
+    const int nb = __builtin_amdgcn_update_dpp(ib, ia, 0x128, 0xF, 0x3, false);
+    const int na = __builtin_amdgcn_update_dpp(ia, ib, 0x128, 0xF, 0xC, false);
+    a = __int_as_float(na);
+    b = __int_as_float(nb);
+  } else if constexpr (D == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)ia, (unsigned)ib, false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+  } else {
+    static_assert(D == 32, "lane distance");
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)ia, (unsigned)ib, false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void xl_exchange(cx<float>& a, cx<float>& b) {
+  xl_exchange<D>(a.re, b.re);
+  xl_exchange<D>(a.im, b.im);
+}
+
+// v[j] of lane i  ->  v[i] of lane j, for the 8 lanes base + 8 i
+__device__ __forceinline__ void xl_transpose8(cx<float>* v) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (!(k & 1)) xl_exchange<8>(v[k], v[k | 1]);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (!(k & 2)) xl_exchange<16>(v[k], v[k | 2]);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (!(k & 4)) xl_exchange<32>(v[k], v[k | 4]);
+}
+
+// strided pass of lane i over its points i + 8 j; w[j] = W_64^(i j), j = 1..7
+template <bool INV>
+__device__ __forceinline__ void xl_strided(cx<float>* v, const cx<float>* w) {
+  if constexpr (INV) {
+#pragma unroll
+    for (int j = 1; j < 8; ++j) v[j] = mul_fma(conjg(w[j]), v[j]);
+  }
+  dft8<float, INV>(v);
+  if constexpr (!INV) {
+#pragma unroll
+    for (int j = 1; j < 8; ++j) v[j] = mul_fma(w[j], v[j]);
+  }
+}
+
+// LDS slot of tile element (r, c), 64 x 64 tile: unpadded rows, the column
+// XOR-swizzled by 9 (r mod 8).  A wave's 8-lane-group accesses of the row phase
+// (rows 8 w .. 8 w + 7, columns 8 i + j or i + 8 j) and of the column phase
+// (columns 8 w .. 8 w + 7, rows i + 8 j) then fall in distinct banks.
+__device__ __forceinline__ int xl_addr(int r, int c) { return r * 64 + (c ^ (9 * (r & 7))); }
+
 // The same passes over a block of LINES independent length-N lines (a strip of
 // rows or a block of columns of a tile too large for one workgroup's LDS).
 // COLS = false: line l holds A[l * LS + p]; COLS = true: A[p * LS + l].

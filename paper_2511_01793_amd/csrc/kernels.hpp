@@ -213,40 +213,18 @@ struct PxLayout {
   __device__ static void origin(int tid, int rd, int& r0, int& c0) { blk_origin<M, V>(tid, rd, r0, c0); }
 };
 
-// PF: the next round's values are loaded before this round's arithmetic, so
-// their latency hides behind it (one round of values more in registers).
-template <int M, class LY, int L, bool DIRECT, class LOAD, bool PF = false>
+template <int M, class LY, int L, bool DIRECT, class LOAD>
 __device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int tid, int row0,
                                                 LOAD load, float qqmax, float zmax) {
   const size_t base = (size_t)s * M * M;
   const bool slot_den = a.pden_slot != nullptr;
-  cx<float> qn[4], zn[4], Rn[4];
-  if constexpr (PF) {
-    int r0, c0;
-    LY::origin(tid, 0, r0, c0);
-    load(0, r0 + row0, c0, qn, zn, Rn);
-  }
 #pragma unroll
   for (int rd = 0; rd < LY::ROUNDS; ++rd) {
     int r0, c0;
     LY::origin(tid, rd, r0, c0);
     r0 += row0;
     cx<float> q[4], zz[4], R[4];
-    if constexpr (PF) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        q[e] = qn[e];
-        zz[e] = zn[e];
-        R[e] = Rn[e];
-      }
-      if (rd + 1 < LY::ROUNDS) {
-        int r1, c1;
-        LY::origin(tid, rd + 1, r1, c1);
-        load(rd + 1, r1 + row0, c1, qn, zn, Rn);
-      }
-    } else {
-      load(rd, r0, c0, q, zz, R);
-    }
+    load(rd, r0, c0, q, zz, R);
     // per pixel: |Q|^2, u, D = |Q|^2 + u, conj(Q) R (shared by the coarse-grid residual
     // g = conj(Q)(R - Q z) = conj(Q) R - |Q|^2 z and the object numerator)
     float q2[4], u[4], D[4];
@@ -342,8 +320,7 @@ __device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int ti
 template <int M, int V, int L, bool DIRECT = false, class LOAD>
 __device__ __forceinline__ void pixel_update(const StepArgs& a, int s, int tid, LOAD load,
                                              float qqmax, float zmax) {
-  pixel_update_ly<M, PxLayout<M, V>, L, DIRECT, LOAD, (Plan<M, V>::PF != 0)>(a, s, tid, 0, load,
-                                                                            qqmax, zmax);
+  pixel_update_ly<M, PxLayout<M, V>, L, DIRECT, LOAD>(a, s, tid, 0, load, qqmax, zmax);
 }
 
 // modulus projection of one pixel in transform order: Psi' = a Psi/|Psi|
@@ -397,6 +374,15 @@ __device__ __forceinline__ float project_px(cx<float>& P, float dval, float2* ph
 // Returns the slot's sampled misfit (in thread 0).
 // STAGE: the twiddle table is loaded here (its load goes out beside the slot's,
 // its LDS copy is written before the first barrier) instead of by the caller.
+//
+// Plans with register-resident passes (XL; m = 64, 8 * 8 split, 1024 threads):
+// the loads, the exit waves and the per-pixel phase are the LDS plan's, the
+// tile in LDS in the swizzled layout of xl_addr.  Waves 0..7 transform it, wave
+// w holding rows 8 w .. 8 w + 7 in the row phase and columns 8 w .. 8 w + 7 in
+// the column phase (a line in 8 lanes, 8 points per lane), so the tile goes
+// through LDS between the row and the column phase only; waves 8..15 meanwhile
+// put the pattern's amplitudes in LDS in the column phase's order.  The sampled
+// misfit sums the same per-pixel terms as the LDS plans, in another order.
 template <int M, int V, int L, bool DIRECT = false, bool STAGE = false>
 __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>* A,
                                            cx<float>* tws, float* redf, double* redd,
@@ -404,6 +390,17 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
   using P = Px<M, V>;
   constexpr int R = P::ROUNDS, NT = P::NT, LS = P::LS;
   static_assert(M <= NT, "one twiddle per thread");
+  constexpr bool XL = Plan<M, V>::XL != 0;
+  static_assert(!XL || (M == 64 && Plan<M, V>::R1 == 8 && Plan<M, V>::R2 == 8 && NT == 1024),
+                "register-pass plan");
+  // LDS slot of tile element (r, c)
+  auto at = [](int r, int c) {
+    if constexpr (XL) {
+      return xl_addr(r, c);
+    } else {
+      return r * LS + c;
+    }
+  };
   cx<float> twv{0.f, 0.f};
   if constexpr (STAGE) {
     if (tid < M) twv = ld(a.tw, tid);
@@ -420,6 +417,7 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
   using CP = ColPass<M, V>;
   cx<float> qc[P::CACHE ? 4 : 1], zc[P::CACHE ? 4 : 1];
   float amp[CP::PTS];
+  float ampv[XL ? 8 : 1];
   float q2m = 0.f, z2m = 0.f;
   auto load_amps = [&]() {
 #pragma unroll
@@ -444,7 +442,13 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
       zz[2 * i + 1] = ld(zwin, (size_t)(r0 + i) * n + c0 + 1);
     }
     // the intensities go out behind the first exit-wave loads, which are needed first
-    if constexpr (AS == 0) {
+    if constexpr (XL) {
+      // waves 8..15: eight amplitudes each, coalesced (element (tid - 512) + 512 j)
+      if (rd == 0 && tid >= 512) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ampv[j] = dk[(tid - 512) + 512 * j];
+      }
+    } else if constexpr (AS == 0) {
       if (rd == 0) load_amps();
     }
 #pragma unroll
@@ -455,7 +459,7 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
       }
       q2m = fmaxf(q2m, norm2(q[e]));
       z2m = fmaxf(z2m, norm2(zz[e]));
-      A[(r0 + (e >> 1)) * LS + c0 + (e & 1)] = mul(q[e], zz[e]);
+      A[at(r0 + (e >> 1), c0 + (e & 1))] = mul(q[e], zz[e]);
     }
   }
   if constexpr (STAGE) {
@@ -465,31 +469,94 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
   // before they are read in the per-pixel phase
   wave_max2_to_lds<NT>(q2m, z2m, redf, tid);
   __syncthreads();
-  // the forward transform's first three passes (rows, rows, columns)
-  fft_pass<float, M, V, false, true, false>(A, tws, tid);
-  __syncthreads();
-  if constexpr (AS == 1) load_amps();
-  fft_pass<float, M, V, false, false, false>(A, tws, tid);
-  __syncthreads();
-  if constexpr (AS == 2) load_amps();
-  fft_pass<float, M, V, false, true, true>(A, tws, tid);
-  __syncthreads();
-  if constexpr (AS == 3) load_amps();
-  // last forward pass, modulus projection, first inverse pass, in registers
   double acc = 0.0;
-  float2* ph = a.phase ? a.phase + (size_t)k * M * M : nullptr;
-  fft_pass_pair<float, M, V>(A, tid, [&](int e, cx<float>& v) {
-    float2* pe = nullptr;
-    if (ph) {
-      const int w = tid + (e / CP::R1) * CP::NT;
-      pe = ph + (CP::R1 * (w / M) + e % CP::R1) * M + w % M;
+  if constexpr (XL) {
+    // amplitudes in transform order, row stride m + 1 (the column phase's reads
+    // are then bank-conflict free)
+    __shared__ float ampl[M * (M + 1)];
+    const int ln = tid & 63, wv = tid >> 6, lo = ln & 7, gi = ln >> 3;
+    const int r = 8 * wv + lo, C = 8 * wv + lo;
+    cx<float> v[8], w[8];
+    if (wv < 8) {
+      // forward row passes: lane gi of row r takes the points gi + 8 j
+#pragma unroll
+      for (int j = 1; j < 8; ++j) w[j] = tws[gi * j];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = A[xl_addr(r, gi + 8 * j)];
+      xl_strided<false>(v, w);
+      xl_transpose8(v);
+      dft8<float, false>(v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) A[xl_addr(r, 8 * gi + j)] = v[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = (tid - 512) + 512 * j;
+        ampl[(e / M) * (M + 1) + e % M] = ampv[j];
+      }
     }
-    acc += (double)project_amp<M>(v, amplitude(amp[e]), pe, a.phase_write != 0);
-  });
-  acc = wave_sum(acc);
-  if ((tid & 63) == 0) redd[tid >> 6] = acc;
-  __syncthreads();
-  fft2_inverse_tail<float, M, V>(A, tws, tid);
+    __syncthreads();
+    if (wv < 8) {
+      // forward column passes, projection, inverse column passes; each lane
+      // writes back the elements it read
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = A[xl_addr(gi + 8 * j, C)];
+      xl_strided<false>(v, w);
+      xl_transpose8(v);
+      dft8<float, false>(v);
+      float2* ph = a.phase ? a.phase + (size_t)k * M * M : nullptr;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        float2* pe = ph ? ph + (8 * gi + j) * M + C : nullptr;
+        acc += (double)project_amp<M>(v[j], amplitude(ampl[(8 * gi + j) * (M + 1) + C]), pe,
+                                      a.phase_write != 0);
+      }
+      dft8<float, true>(v);
+      xl_transpose8(v);
+      xl_strided<true>(v, w);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) A[xl_addr(gi + 8 * j, C)] = v[j];
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) redd[tid >> 6] = acc;
+    __syncthreads();
+    if (wv < 8) {
+      // inverse row passes; the natural-order result replaces the wave's own rows
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = A[xl_addr(r, 8 * gi + j)];
+      dft8<float, true>(v);
+      xl_transpose8(v);
+      xl_strided<true>(v, w);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) A[xl_addr(r, gi + 8 * j)] = v[j];
+    }
+    __syncthreads();
+  } else {
+    // the forward transform's first three passes (rows, rows, columns)
+    fft_pass<float, M, V, false, true, false>(A, tws, tid);
+    __syncthreads();
+    if constexpr (AS == 1) load_amps();
+    fft_pass<float, M, V, false, false, false>(A, tws, tid);
+    __syncthreads();
+    if constexpr (AS == 2) load_amps();
+    fft_pass<float, M, V, false, true, true>(A, tws, tid);
+    __syncthreads();
+    if constexpr (AS == 3) load_amps();
+    // last forward pass, modulus projection, first inverse pass, in registers
+    float2* ph = a.phase ? a.phase + (size_t)k * M * M : nullptr;
+    fft_pass_pair<float, M, V>(A, tid, [&](int e, cx<float>& v) {
+      float2* pe = nullptr;
+      if (ph) {
+        const int w = tid + (e / CP::R1) * CP::NT;
+        pe = ph + (CP::R1 * (w / M) + e % CP::R1) * M + w % M;
+      }
+      acc += (double)project_amp<M>(v, amplitude(amp[e]), pe, a.phase_write != 0);
+    });
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) redd[tid >> 6] = acc;
+    __syncthreads();
+    fft2_inverse_tail<float, M, V>(A, tws, tid);
+  }
   float qqmax, zmax;
   lds_max2<NT>(redf, qqmax, zmax);
   pixel_update<M, V, L, DIRECT>(
@@ -507,8 +574,8 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
             zz[2 * i] = ld(zwin, (size_t)(r0 + i) * n + c0);
             zz[2 * i + 1] = ld(zwin, (size_t)(r0 + i) * n + c0 + 1);
           }
-          Rv[2 * i] = A[(r0 + i) * LS + c0];
-          Rv[2 * i + 1] = A[(r0 + i) * LS + c0 + 1];
+          Rv[2 * i] = A[at(r0 + i, c0)];
+          Rv[2 * i + 1] = A[at(r0 + i, c0 + 1)];
         }
       },
       qqmax, zmax);

@@ -10,9 +10,12 @@
 // another split reorders the DFT arithmetic (same transform, other rounding)
 // and lays the intensities out in its own transform order.
 //
-// PF = 1: the per-pixel phase loads each round's values one round ahead (a gain
-// for the two-round 512-thread plan at m = 64; at m = 128 the extra registers
-// cost more than the hidden latency).
+// XL = 1: the patch kernel keeps the tile in registers through the two passes
+// of each dimension and transposes a line's 8 lanes with cross-lane moves, so
+// the tile goes through LDS between the row and the column phase instead of
+// after every pass (m = 64, 8 * 8 split, 1024 threads only).  The plan's other
+// kernels use the LDS passes.  The arithmetic is the same either way, so the
+// results are bitwise those of the other plans with the same split.
 // AMP is where the patch kernel issues the loads of the measured intensities:
 // 0 with the exit-wave loads at the start, k > 0 after the k-th forward pass.
 // Plans whose registers are tight at 1024 threads issue them late, so the
@@ -27,17 +30,17 @@
 namespace emg {
 
 template <int M, int V> struct Plan;
-template <> struct Plan<32, 0> { static constexpr int R1 = 8, R2 = 4, NT = 256; static constexpr int AMP = 0, PF = 0; };
-template <> struct Plan<32, 1> { static constexpr int R1 = 4, R2 = 8, NT = 256; static constexpr int AMP = 0, PF = 0; };
-template <> struct Plan<64, 0> { static constexpr int R1 = 8, R2 = 8, NT = 1024; static constexpr int AMP = 0, PF = 0; };
-template <> struct Plan<64, 1> { static constexpr int R1 = 16, R2 = 4, NT = 1024; static constexpr int AMP = 2, PF = 0; };
-template <> struct Plan<64, 2> { static constexpr int R1 = 4, R2 = 16, NT = 1024; static constexpr int AMP = 0, PF = 0; };
-template <> struct Plan<64, 3> { static constexpr int R1 = 8, R2 = 8, NT = 512; static constexpr int AMP = 0, PF = 1; };
-template <> struct Plan<128, 0> { static constexpr int R1 = 16, R2 = 8, NT = 1024; static constexpr int AMP = 3, PF = 0; };
-template <> struct Plan<128, 1> { static constexpr int R1 = 8, R2 = 16, NT = 1024; static constexpr int AMP = 2, PF = 0; };
-template <> struct Plan<128, 2> { static constexpr int R1 = 16, R2 = 8, NT = 512; static constexpr int AMP = 0, PF = 0; };
+template <> struct Plan<32, 0> { static constexpr int R1 = 8, R2 = 4, NT = 256; static constexpr int AMP = 0, XL = 0; };
+template <> struct Plan<32, 1> { static constexpr int R1 = 4, R2 = 8, NT = 256; static constexpr int AMP = 0, XL = 0; };
+template <> struct Plan<64, 0> { static constexpr int R1 = 8, R2 = 8, NT = 1024; static constexpr int AMP = 0, XL = 0; };
+template <> struct Plan<64, 1> { static constexpr int R1 = 16, R2 = 4, NT = 1024; static constexpr int AMP = 2, XL = 0; };
+template <> struct Plan<64, 2> { static constexpr int R1 = 4, R2 = 16, NT = 1024; static constexpr int AMP = 0, XL = 0; };
+template <> struct Plan<64, 3> { static constexpr int R1 = 8, R2 = 8, NT = 1024; static constexpr int AMP = 0, XL = 1; };
+template <> struct Plan<128, 0> { static constexpr int R1 = 16, R2 = 8, NT = 1024; static constexpr int AMP = 3, XL = 0; };
+template <> struct Plan<128, 1> { static constexpr int R1 = 8, R2 = 16, NT = 1024; static constexpr int AMP = 2, XL = 0; };
+template <> struct Plan<128, 2> { static constexpr int R1 = 16, R2 = 8, NT = 512; static constexpr int AMP = 0, XL = 0; };
 // m = 256: the tile exceeds LDS; strips of 16 lines per workgroup (see kernels256.hpp)
-template <> struct Plan<256, 0> { static constexpr int R1 = 16, R2 = 16, NT = 256; static constexpr int AMP = 0, PF = 0; };
+template <> struct Plan<256, 0> { static constexpr int R1 = 16, R2 = 16, NT = 256; static constexpr int AMP = 0, XL = 0; };
 
 template <int M> struct PlanCount;
 template <> struct PlanCount<32> { static constexpr int value = 2; };
@@ -53,7 +56,7 @@ inline bool fft_plan_desc(int m, int v, int* r1, int* r2, int* nt) {
     int m, v, r1, r2, nt;
   };
   static const D t[] = {{32, 0, 8, 4, 256},   {32, 1, 4, 8, 256},   {64, 0, 8, 8, 1024},
-                        {64, 1, 16, 4, 1024}, {64, 2, 4, 16, 1024}, {64, 3, 8, 8, 512},
+                        {64, 1, 16, 4, 1024}, {64, 2, 4, 16, 1024}, {64, 3, 8, 8, 1024},
                         {128, 0, 16, 8, 1024}, {128, 1, 8, 16, 1024}, {128, 2, 16, 8, 512},
                         {256, 0, 16, 16, 256}};
   for (const D& d : t)
