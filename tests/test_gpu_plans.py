@@ -177,3 +177,39 @@ def test_group_members_with_different_plans_match_individual_runs():
     g.close()
     for r in recs:
         r.close()
+
+
+@pytest.mark.parametrize("path", ["fused", "chain"])
+def test_phase_memory_in_the_register_pass_plan(path):
+    """Zero-bin phase memory through plan (64, 3), whose projection runs in the column phase
+    of the register passes: the first visit of pattern k stores its phases, the second (a
+    constant exit wave: every bin but DC exactly zero) takes them back.  Bitwise the LDS plan
+    with the same split, and the oracle to the step bar."""
+    p = small(64, L=1)
+    say("case: phase memory, register passes", path)
+    rng = np.random.default_rng(17)
+    k = 3
+    Qr = (rng.standard_normal((p.m, p.m)) + 1j * rng.standard_normal((p.m, p.m))).astype(np.complex64)
+    zr = (rng.standard_normal((p.n, p.n)) + 1j * rng.standard_normal((p.n, p.n))).astype(np.complex64)
+    Qc = np.full((p.m, p.m), 0.6 - 0.2j, dtype=np.complex64)
+    zc = np.full((p.n, p.n), 1.0 + 0.1j, dtype=np.complex64)
+    a = amps(p)
+    mem = np.ones((p.n_pos, p.m, p.m), complex)
+    O.step_minibatch(Qr.astype(complex), zr.astype(complex), p.positions, a, [k], alpha=p.alpha,
+                     levels=p.levels, phase_mem=mem)
+    q_ref, z_ref, _ = O.step_minibatch(Qc.astype(complex), zc.astype(complex), p.positions, a, [k],
+                                       alpha=p.alpha, levels=p.levels, phase_mem=mem)
+    out = {}
+    for v in (0, 3):
+        rec = rec_for(p, fft_plan=v, path=path, zero_phase_memory=True, minibatch=1)
+        obj, probe = torch.from_numpy(zr).cuda(), torch.from_numpy(Qr).cuda()
+        rec.step(obj, probe, [k])
+        obj.copy_(torch.from_numpy(zc))
+        probe.copy_(torch.from_numpy(Qc))
+        rec.step(obj, probe, [k])
+        torch.cuda.synchronize()
+        out[v] = (obj, probe)
+        rec.close()
+    assert torch.equal(out[3][0], out[0][0]) and torch.equal(out[3][1], out[0][1])
+    zg, qg = host(out[3][0]), host(out[3][1])
+    assert rel(zg, z_ref) < STEP_TOL and rel(qg, q_ref) < STEP_TOL, (rel(zg, z_ref), rel(qg, q_ref))
