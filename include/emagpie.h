@@ -56,8 +56,9 @@ enum {
   EMAGPIE_PATH_FUSED = 1,  /* fused per-patch kernel + finalize kernel         */
   EMAGPIE_PATH_GRAPH = 2,  /* FUSED launches replayed from a captured hipGraph */
   EMAGPIE_PATH_PERSISTENT = 3, /* one cooperative launch per epoch, grid barriers */
-  EMAGPIE_PATH_AUTO = 4, /* chosen at init by timing FUSED, GRAPH and PERSISTENT epochs
-                            (and CHAIN when minibatch = 1)                           */
+  EMAGPIE_PATH_AUTO = 4, /* chosen at init by timing FUSED and GRAPH epochs (and
+                            CHAIN when minibatch = 1); PERSISTENT only on request: a
+                            cooperative launch slows the process's later launches   */
   EMAGPIE_PATH_CHAIN = 5 /* minibatch 1 only: one workgroup runs the whole sequential
                             sweep, each step applied in place (the paper's literal order,
                             Sec. 3 footnote: positions updated one after another)     */
@@ -135,7 +136,8 @@ emagpie_status emagpie_workspace_size(const emagpie_config* cfg, size_t* bytes);
  * problem shape, init times the candidates on the given intensities and
  * positions with a scratch state held in the workspace: each FFT plan's
  * patch-stage kernel and each finalize shape over minibatches of the epoch-0
- * scan order, then whole epochs of each path; it keeps the fastest and appends
+ * scan order, then whole epochs of each candidate path (fused and graph, and
+ * chain when minibatch = 1); it keeps the fastest and appends
  * it to tune_cache.  The caller's buffers are not touched.  A tune_cache that
  * cannot be read or written is ignored.
  */

@@ -549,10 +549,12 @@ emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* i
     c->cfg.path = saved_path;
     c->cfg.finalize_shape = ep[1] < ep[0] ? second : best;
   }
-  // 3. path: whole epochs on the scratch state
+  // 3. path: whole epochs on the scratch state.  The persistent path is not a
+  // candidate: it was slower on every workload measured, and its cooperative launch
+  // leaves the process's later launches slower (most of all concurrent graph branches,
+  // as in a group sweep), so timing it here would cost the path that wins.
   if (req.path == EMAGPIE_PATH_AUTO) {
-    const int cand[4] = {EMAGPIE_PATH_FUSED, EMAGPIE_PATH_GRAPH, EMAGPIE_PATH_PERSISTENT,
-                         EMAGPIE_PATH_CHAIN};
+    const int cand[3] = {EMAGPIE_PATH_FUSED, EMAGPIE_PATH_GRAPH, EMAGPIE_PATH_CHAIN};
     int best = EMAGPIE_PATH_FUSED;
     for (int p : cand) {
       if (p == EMAGPIE_PATH_CHAIN && B != 1) continue;

@@ -118,7 +118,7 @@ def test_autotune_and_cache(tmp_path):
     assert plan["tuned"] == "timed"
     assert len(plan["fft_us"]) == n_plans(64) and all(t > 0 for t in plan["fft_us"])
     assert len(plan["fin_us"]) == 8 and all(t > 0 for t in plan["fin_us"])
-    assert set(plan["path_ms"]) == {"fused", "graph", "persistent"}
+    assert set(plan["path_ms"]) == {"fused", "graph"}
     assert plan["fft_us"][plan["fft_plan"]] == min(plan["fft_us"])
     # the two fastest shapes alone are compared on whole epochs
     assert plan["fin_us"][plan["finalize_shape"]] <= sorted(plan["fin_us"])[1]
