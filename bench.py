@@ -107,26 +107,35 @@ def time_epochs(rec, obj, probe, K, W, e0=0):
     return (time.perf_counter() - t0) / K
 
 
-def time_to_target(rec, obj, probe, target, max_epochs, at_epoch):
-    """Wall time and epochs until Phi <= target (epoch + misfit per iteration); also
-    Phi after exactly `at_epoch` epochs (the oracle's epoch count)."""
+def time_to_target(rec, obj, probe, target, max_epochs, at_epoch, check_every=10):
+    """GPU time and epochs until Phi <= target (epoch + misfit per iteration); also Phi
+    after exactly `at_epoch` epochs (the oracle's epoch count).  Every epoch's Phi goes to
+    its own device slot and an event follows it on the stream; the host reads the Phi
+    history every `check_every` epochs, so it never stalls the stream in between, and the
+    time to the first epoch with Phi <= target is the event time from the start."""
     import torch
-    phi = torch.empty((), dtype=torch.float64, device="cuda")
+    phis = torch.empty(max_epochs, dtype=torch.float64, device="cuda")
+    start = torch.cuda.Event(enable_timing=True)
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(max_epochs)]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hit, phi_at = None, None
-    for e in range(max_epochs):
-        rec.epoch(obj, probe, e)
-        rec.misfit(obj, probe, out=phi)
-        v = float(phi.item())
-        if hit is None and v <= target:
-            hit = (time.perf_counter() - t0, e + 1, v)
-        if e + 1 == at_epoch:
-            phi_at = v
-        if hit is not None and phi_at is not None:
-            break
+    start.record()
+    hit, phi_at, vals, e = None, None, [], 0
+    while e < max_epochs and (hit is None or phi_at is None):
+        e1 = min(max_epochs, e + check_every)
+        for k in range(e, e1):
+            rec.epoch(obj, probe, k)
+            rec.misfit(obj, probe, out=phis[k])
+            ends[k].record()
+        ends[e1 - 1].synchronize()
+        vals = phis[:e1].tolist()
+        for k in range(e, e1):
+            if hit is None and vals[k] <= target:
+                hit = (start.elapsed_time(ends[k]) / 1e3, k + 1, vals[k])
+            if k + 1 == at_epoch:
+                phi_at = vals[k]
+        e = e1
     if hit is None:
-        hit = (None, max_epochs, v)
+        hit = (None, max_epochs, vals[-1])
     return hit[0], hit[1], hit[2], phi_at
 
 
