@@ -5,7 +5,8 @@
 //
 // One workgroup owns one m x m scan patch in the patch stage: it gathers the
 // object window, forms the exit wave psi = Q . z_k (Def. 2.1), runs the
-// forward 2-D DFT in LDS, projects onto the measured moduli (Def. 2.1,
+// forward 2-D DFT (LDS passes; one m = 64 plan keeps each line in registers
+// across lanes instead), projects onto the measured moduli (Def. 2.1,
 // theta(0) = 0), runs the inverse DFT, and applies the per-pixel surrogate
 // algebra: the MAGPIE coarse correction (Sec. 3.2, Eqs. 12-15, in its
 // block-ratio form), the object numerator conj(Q) R + u z' (Eq. 7 / Eq. 9 as
@@ -19,7 +20,7 @@
 // The chain of minibatches is sequential (each one reads the state the
 // previous one wrote), so at the benchmark's sizes the patch stage is bound by
 // latency, not bandwidth: a patch gets up to 1024 threads (16 waves) and each
-// thread loads its probe, object and amplitude values once, up front.
+// thread issues its probe, object and amplitude loads before any dependent work.
 #pragma once
 
 #include <hip/hip_ext.h>
@@ -471,8 +472,8 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
   __syncthreads();
   double acc = 0.0;
   if constexpr (XL) {
-    // amplitudes in transform order, row stride m + 1 (the column phase's reads
-    // are then bank-conflict free)
+    // measured amplitudes sqrt(max(d, 0)) in transform order, row stride m + 1
+    // (the column phase's reads are then bank-conflict free)
     __shared__ float ampl[M * (M + 1)];
     const int ln = tid & 63, wv = tid >> 6, lo = ln & 7, gi = ln >> 3;
     const int r = 8 * wv + lo, C = 8 * wv + lo;
@@ -492,7 +493,7 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int e = (tid - 512) + 512 * j;
-        ampl[(e / M) * (M + 1) + e % M] = ampv[j];
+        ampl[(e / M) * (M + 1) + e % M] = amplitude(ampv[j]);
       }
     }
     __syncthreads();
@@ -508,7 +509,7 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         float2* pe = ph ? ph + (8 * gi + j) * M + C : nullptr;
-        acc += (double)project_amp<M>(v[j], amplitude(ampl[(8 * gi + j) * (M + 1) + C]), pe,
+        acc += (double)project_amp<M>(v[j], ampl[(8 * gi + j) * (M + 1) + C], pe,
                                       a.phase_write != 0);
       }
       dft8<float, true>(v);
