@@ -370,6 +370,53 @@ __device__ __forceinline__ float project_px(cx<float>& P, float dval, float2* ph
 }
 
 // ---------------------------------------------------------------------------
+// pieces of the register-pass plan (m = 64, 8 * 8 split, 1024 threads).  Waves
+// 0..7 transform: wave w holds rows 8 w .. 8 w + 7 in the row phase and columns
+// 8 w .. 8 w + 7 in the column phase, lane lo + 8 gi taking line lo of the
+// wave, 8 points per lane; the tile sits in LDS at xl_addr.  Waves 8..15 stage
+// the pattern's amplitudes in LDS (row stride m + 1) meanwhile.
+// ---------------------------------------------------------------------------
+// twiddles W^(gi j), j = 1..7, of lane group gi: the same in every strided pass
+__device__ __forceinline__ void xl_twiddles(const cx<float>* tws, int gi, cx<float>* w) {
+#pragma unroll
+  for (int j = 1; j < 8; ++j) w[j] = tws[gi * j];
+}
+
+// forward row passes of row r: natural order in, row-transform order out
+__device__ __forceinline__ void xl_rows_forward(cx<float>* A, const cx<float>* w, int r, int gi) {
+  cx<float> v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = A[xl_addr(r, gi + 8 * j)];
+  xl_strided<false>(v, w);
+  xl_transpose8(v);
+  dft8<float, false>(v);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) A[xl_addr(r, 8 * gi + j)] = v[j];
+}
+
+// forward column passes of column C: v[j] is then the spectrum at transform-order
+// row 8 gi + j
+__device__ __forceinline__ void xl_cols_forward(const cx<float>* A, const cx<float>* w, int C,
+                                                int gi, cx<float>* v) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = A[xl_addr(gi + 8 * j, C)];
+  xl_strided<false>(v, w);
+  xl_transpose8(v);
+  dft8<float, false>(v);
+}
+
+// waves 8..15: the amplitudes sqrt(max(d, 0)) of dk (transform order) to LDS;
+// ampv holds the thread's eight intensities (element (tid - 512) + 512 j)
+template <int M>
+__device__ __forceinline__ void xl_stage_amps(float* ampl, const float* ampv, int tid) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int e = (tid - 512) + 512 * j;
+    ampl[(e / M) * (M + 1) + e % M] = amplitude(ampv[j]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // the whole patch stage for slot s, LDS-resident
 // ---------------------------------------------------------------------------
 // Returns the slot's sampled misfit (in thread 0).
@@ -479,32 +526,16 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
     const int r = 8 * wv + lo, C = 8 * wv + lo;
     cx<float> v[8], w[8];
     if (wv < 8) {
-      // forward row passes: lane gi of row r takes the points gi + 8 j
-#pragma unroll
-      for (int j = 1; j < 8; ++j) w[j] = tws[gi * j];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = A[xl_addr(r, gi + 8 * j)];
-      xl_strided<false>(v, w);
-      xl_transpose8(v);
-      dft8<float, false>(v);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) A[xl_addr(r, 8 * gi + j)] = v[j];
+      xl_twiddles(tws, gi, w);
+      xl_rows_forward(A, w, r, gi);
     } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int e = (tid - 512) + 512 * j;
-        ampl[(e / M) * (M + 1) + e % M] = amplitude(ampv[j]);
-      }
+      xl_stage_amps<M>(ampl, ampv, tid);
     }
     __syncthreads();
     if (wv < 8) {
       // forward column passes, projection, inverse column passes; each lane
       // writes back the elements it read
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = A[xl_addr(gi + 8 * j, C)];
-      xl_strided<false>(v, w);
-      xl_transpose8(v);
-      dft8<float, false>(v);
+      xl_cols_forward(A, w, C, gi, v);
       float2* ph = a.phase ? a.phase + (size_t)k * M * M : nullptr;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
