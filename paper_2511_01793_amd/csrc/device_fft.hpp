@@ -375,8 +375,8 @@ __device__ __forceinline__ void xl_strided(cx<float>* v, const cx<float>* w) {
 // (columns 8 w .. 8 w + 7, rows i + 8 j) then fall in distinct banks.
 __device__ __forceinline__ int xl_addr(int r, int c) { return r * 64 + (c ^ (9 * (r & 7))); }
 
-// The same passes over a block of LINES independent length-N lines (a strip of
-// rows or a block of columns of a tile too large for one workgroup's LDS).
+// The LDS passes of fft_pass over a block of LINES independent length-N lines (a
+// strip of rows or a block of columns of a tile too large for one workgroup's LDS).
 // COLS = false: line l holds A[l * LS + p]; COLS = true: A[p * LS + l].
 template <typename T, int N, int R1, int R2, int LINES, int NT, int LS, bool INV, bool STRIDED,
           bool COLS>

@@ -428,7 +428,8 @@ __device__ __forceinline__ void xl_stage_amps(float* ampl, const float* ampv, in
 // tile in LDS in the swizzled layout of xl_addr.  Waves 0..7 transform it, wave
 // w holding rows 8 w .. 8 w + 7 in the row phase and columns 8 w .. 8 w + 7 in
 // the column phase (a line in 8 lanes, 8 points per lane), so the tile goes
-// through LDS between the row and the column phase only; waves 8..15 meanwhile
+// through LDS between the row and the column phases, not between the two passes
+// of a dimension; waves 8..15 meanwhile
 // put the pattern's amplitudes in LDS in the column phase's order.  The sampled
 // misfit sums the same per-pixel terms as the LDS plans, in another order.
 template <int M, int V, int L, bool DIRECT = false, bool STAGE = false>
