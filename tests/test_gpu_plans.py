@@ -213,3 +213,23 @@ def test_phase_memory_in_the_register_pass_plan(path):
     assert torch.equal(out[3][0], out[0][0]) and torch.equal(out[3][1], out[0][1])
     zg, qg = host(out[3][0]), host(out[3][1])
     assert rel(zg, z_ref) < STEP_TOL and rel(qg, q_ref) < STEP_TOL, (rel(zg, z_ref), rel(qg, q_ref))
+
+
+@pytest.mark.parametrize("L, joint, update_probe", [(1, True, True), (3, True, True),
+                                                    (2, False, True), (2, True, False)])
+def test_register_pass_plan_in_every_mode(L, joint, update_probe):
+    """Plan (64, 3) against the LDS plan with the same split, bit for bit, for each multigrid
+    depth, the rPIE step (no joint step) and the non-blind step (probe fixed); and its
+    MAGPIE z+ output (mg_cycle)."""
+    p = small(64, L=L)
+    say("case: register passes", L, joint, update_probe)
+    out = {}
+    for v in (0, 3):
+        o, q, _ = run_epochs(p, epochs=2, fft_plan=v, joint_step=joint, update_probe=update_probe)
+        rec = rec_for(p, fft_plan=v, joint_step=joint, update_probe=update_probe)
+        zp = rec.mg_cycle(o.clone(), q.clone(), np.arange(p.minibatch, dtype=np.int32))
+        torch.cuda.synchronize()
+        out[v] = (o, q, zp)
+        rec.close()
+    for a, b in zip(out[0], out[3]):
+        assert torch.equal(a, b)
