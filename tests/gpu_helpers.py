@@ -32,7 +32,7 @@ def problem(name="tiny", **kw):
 
 
 def make_rec(p, path="fused", levels=None, minibatch=None, alpha=None, update_probe=True, seed=3,
-             joint_step=True):
+             joint_step=True, fft_plan=0, finalize_shape=0):
     import torch
     import paper_2511_01793_amd.emagpie as E
     d = torch.from_numpy(p.intensities).cuda()
@@ -40,7 +40,8 @@ def make_rec(p, path="fused", levels=None, minibatch=None, alpha=None, update_pr
                            minibatch=p.minibatch if minibatch is None else minibatch,
                            levels=p.levels if levels is None else levels,
                            alpha=p.alpha if alpha is None else alpha, alpha_z=p.alpha_z,
-                           update_probe=update_probe, joint_step=joint_step, path=path, seed=seed)
+                           update_probe=update_probe, joint_step=joint_step, path=path, seed=seed,
+                           fft_plan=fft_plan, finalize_shape=finalize_shape)
     return rec
 
 

@@ -15,11 +15,15 @@ def c2():
     return problem("c2")
 
 
-@pytest.mark.parametrize("path", ["graph", "persistent"])
-def test_c2_minibatch_step_parity(c2, path):
+# (path, FFT plan, finalize shape): the default plan on two launch strategies, and the
+# configuration the autotuner picks for this workload (register-resident passes, 16^2 tiles
+# in banded order, fused launches)
+@pytest.mark.parametrize("path, plan, shape", [("graph", 0, 0), ("persistent", 0, 0),
+                                               ("fused", 3, 5)])
+def test_c2_minibatch_step_parity(c2, path, plan, shape):
     p = c2
-    print("case: c2 step", path, flush=True)
-    rec = make_rec(p, path=path, seed=p.seed)
+    print("case: c2 step", path, plan, shape, flush=True)
+    rec = make_rec(p, path=path, seed=p.seed, fft_plan=plan, finalize_shape=shape)
     obj, probe = init_state(p, rec)
     a = amps(p)
     perm = O.permutation(p.seed, 0, p.n_pos)
@@ -56,7 +60,9 @@ def c3():
     return problem("c3")
 
 
-def test_c3_minibatch_step_parity_three_levels(c3):
+# the default plan, and the configuration the autotuner picks for this workload
+@pytest.mark.parametrize("path, plan, shape", [("graph", 0, 0), ("fused", 1, 2)])
+def test_c3_minibatch_step_parity_three_levels(c3, path, plan, shape):
     # 1024^2 object, 128^2 probe, 10000 positions, minibatch 256, three levels; full
     # minibatches from mid-reconstruction states.  At the initial guess (z = 1, smooth
     # zero-phase probe) almost every Fourier bin of the exit wave lies below float32
@@ -64,8 +70,8 @@ def test_c3_minibatch_step_parity_three_levels(c3):
     # with 1e7-photon data the measured amplitudes at those bins are not negligible; the
     # comparison therefore starts after one sweep.
     p = c3
-    print("case: c3 step", flush=True)
-    rec = make_rec(p, path="graph", seed=p.seed)
+    print("case: c3 step", path, plan, shape, flush=True)
+    rec = make_rec(p, path=path, seed=p.seed, fft_plan=plan, finalize_shape=shape)
     obj, probe = init_state(p, rec)
     rec.epoch(obj, probe, 0)
     a = amps(p)
