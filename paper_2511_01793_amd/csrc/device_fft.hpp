@@ -316,12 +316,19 @@ __device__ __forceinline__ void fft_pass_pair(cx<T>* A, int tid, F f) {
 // D bit clear take the partner's a into b, lanes with it set take the partner's
 // b into a.  D = 8: two DPP moves (row rotation by 8 within 16-lane rows, the
 // bank mask picking the receiving half); D = 16, 32: one lane-swap instruction.
+// DPP controls: rotate right by 8 lanes within each 16-lane row (lane l reads
+// lane l ^ 8), all four rows enabled, and the bank masks (banks are 4-lane
+// groups of a row) of its lower and upper 8 lanes
+constexpr int kDppRowRor8 = 0x128, kDppAllRows = 0xF, kDppBanksLow8 = 0x3, kDppBanksHigh8 = 0xC;
+
 template <int D>
 __device__ __forceinline__ void xl_exchange(float& a, float& b) {
   const int ia = __float_as_int(a), ib = __float_as_int(b);
   if constexpr (D == 8) {
-    const int nb = __builtin_amdgcn_update_dpp(ib, ia, 0x128, 0xF, 0x3, false);
-    const int na = __builtin_amdgcn_update_dpp(ia, ib, 0x128, 0xF, 0xC, false);
+    const int nb =
+        __builtin_amdgcn_update_dpp(ib, ia, kDppRowRor8, kDppAllRows, kDppBanksLow8, false);
+    const int na =
+        __builtin_amdgcn_update_dpp(ia, ib, kDppRowRor8, kDppAllRows, kDppBanksHigh8, false);
     a = __int_as_float(na);
     b = __int_as_float(nb);
   } else if constexpr (D == 16) {
