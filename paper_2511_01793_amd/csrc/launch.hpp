@@ -167,7 +167,7 @@ struct Launchers {
   static hipError_t chain(int v, int L, const StepArgs& a, int n_steps, hipStream_t s);
 };
 
-// m = 256 (kernels256.hpp, kernels_m256.hip): the same members; the tile exceeds
+// m = 256 (kernels_m256.hip): the same members; the tile exceeds
 // LDS, so a patch runs as row strips and column blocks over a.stack.  Members with
 // no m = 256 form return hipErrorInvalidValue (the host rejects those requests
 // before launching).

@@ -39,7 +39,7 @@ template <> struct Plan<64, 3> { static constexpr int R1 = 8, R2 = 8, NT = 1024;
 template <> struct Plan<128, 0> { static constexpr int R1 = 16, R2 = 8, NT = 1024; static constexpr int AMP = 3, XL = 0; };
 template <> struct Plan<128, 1> { static constexpr int R1 = 8, R2 = 16, NT = 1024; static constexpr int AMP = 2, XL = 0; };
 template <> struct Plan<128, 2> { static constexpr int R1 = 16, R2 = 8, NT = 512; static constexpr int AMP = 0, XL = 0; };
-// m = 256: the tile exceeds LDS; strips of 16 lines per workgroup (see kernels256.hpp)
+// m = 256: the tile exceeds LDS; strips of 16 lines per workgroup (kernels_m256.hip)
 template <> struct Plan<256, 0> { static constexpr int R1 = 16, R2 = 16, NT = 256; static constexpr int AMP = 0, XL = 0; };
 
 template <int M> struct PlanCount;

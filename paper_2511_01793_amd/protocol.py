@@ -1,4 +1,4 @@
-"""Reconstruction protocol of the paper's numerical experiments (Sec. 5.1).
+"""Reconstruction protocol of the paper's numerical experiments (Sec. 4.1).
 
 * quality metrics: the residual Phi of Eq. 1 (evaluated by the library's misfit kernel) and
   the magnitude error || |z| - |z*| ||_2 over the whole object;
@@ -6,7 +6,7 @@
   that stops once the residual falls below a fraction of the misfit of the ground truth;
 * a driver that runs eMAGPIE (joint step of Eq. 6, multigrid object step) or the rPIE
   comparator (Eq. 2: the same kernels, one level, no joint step) epoch by epoch on the GPU;
-* the synthetic analogues of the overlap study (Sec. 5.2) and the noise study (Sec. 5.3):
+* the synthetic analogues of the overlap study (Sec. 4.2) and the noise study (Sec. 4.3):
   ``python -m paper_2511_01793_amd.protocol --study overlap|noise``.
 
 Reading of the moving-average rule: the printed condition compares the moving average with
@@ -30,7 +30,7 @@ __all__ = ["MovingAverageStop", "below_floor", "magnitude_error", "reconstruct",
 
 
 class MovingAverageStop:
-    """Moving-average stopping rule (Sec. 5.1) with window w and patience p."""
+    """Moving-average stopping rule (Sec. 4.1) with window w and patience p."""
 
     def __init__(self, window: int = 5, patience: int = 10):
         if window < 1 or patience < 1:
@@ -60,13 +60,13 @@ class MovingAverageStop:
 
 
 def below_floor(residual: float, floor: float, factor: float = 0.9) -> bool:
-    """Noise-floor rule (Sec. 5.3): stop once the residual is below factor x the misfit of
+    """Noise-floor rule (Sec. 4.3): stop once the residual is below factor x the misfit of
     the ground-truth object and probe on the same (noisy) data."""
     return residual < factor * floor
 
 
 def magnitude_error(z, z_true, align_scale: bool = False) -> float:
-    """|| |z| - |z*| ||_2 over all pixels (the error metric of Sec. 5.1), in float64.
+    """|| |z| - |z*| ||_2 over all pixels (the error metric of Sec. 4.1), in float64.
 
     With align_scale, |z| is first multiplied by the c >= 0 that minimises the norm
     (c = <|z|, |z*|> / <|z|, |z|>): blind reconstructions are determined only up to

@@ -246,12 +246,12 @@ def make_c5(count: int = 16, seed: int = 1005) -> list:
 
 
 # --------------------------------------------------------------------------
-# Stand-ins for the inputs of the paper's synthetic experiments (Sec. 5.1)
+# Stand-ins for the inputs of the paper's synthetic experiments (Sec. 4.1)
 # --------------------------------------------------------------------------
 
 def textured_object(n: int, rng: np.random.Generator, n_blobs: int = 400) -> np.ndarray:
     """Object with the value ranges of the paper's test object: |z*| in [0, 1] and arg z* in
-    [0, pi/2] (Sec. 5.1), each channel a min-max normalised sum of n_blobs Gaussian blobs of
+    [0, pi/2] (Sec. 4.1), each channel a min-max normalised sum of n_blobs Gaussian blobs of
     width U[n/256, n/24] (finer texture than make_object, standing in for natural images)."""
     yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
 
@@ -276,7 +276,7 @@ def textured_object(n: int, rng: np.random.Generator, n_blobs: int = 400) -> np.
 
 def zone_plate_probe(m: int, outer: float = 0.1875, stop: float = 0.4,
                      spot: float = 0.25) -> np.ndarray:
-    """Defocused Fresnel-zone-plate illumination (stand-in for the simulated FZP of Sec. 5.1).
+    """Defocused Fresnel-zone-plate illumination (stand-in for the simulated FZP of Sec. 4.1).
 
     A zone plate with a central stop passes an annulus of spatial frequencies,
     stop * outer * m <= |k| <= outer * m (cycles per window).  Out of focus, each frequency
@@ -300,7 +300,7 @@ def zone_plate_probe(m: int, outer: float = 0.1875, stop: float = 0.4,
 def perturbed_initial_probe(probe_true: np.ndarray, rng: np.random.Generator, *,
                             sigma_amp: float = 2.0, ramp: float = 7.0, defocus: float = 0.6,
                             astig: float = 0.2, noise: float = 0.01) -> np.ndarray:
-    """Initial probe from the ground truth (Sec. 5.1): Fourier-domain Gaussian blur of |Q*|,
+    """Initial probe from the ground truth (Sec. 4.1): Fourier-domain Gaussian blur of |Q*|,
     a random linear phase ramp of total size `ramp` rad across the window, defocus and
     astigmatism terms, plus complex noise of relative amplitude `noise`.
 
@@ -338,7 +338,7 @@ def overlap_positions(n: int, m: int, overlap: float, rng: np.random.Generator,
 
 
 def photon_scale_for_noise(clean: np.ndarray, percent: float) -> float:
-    """Factor s such that Poisson counts of s * clean have expected Noise% (Sec. 5.1) equal to
+    """Factor s such that Poisson counts of s * clean have expected Noise% (Sec. 4.1) equal to
     `percent`: the Poisson variance equals the mean, so E sum n^2 = s sum f and
     Noise%^2 / 100^2 = sum f / (s sum f^2)."""
     c = np.asarray(clean, np.float64)
@@ -348,10 +348,10 @@ def photon_scale_for_noise(clean: np.ndarray, percent: float) -> float:
 def make_protocol_problem(*, overlap: float, noise_percent: float | None = None, n: int = 512,
                           m: int = 128, alpha: float | None = None, B: int = 1, L: int = 1,
                           seed: int = 2025) -> Problem:
-    """Synthetic analogue of the paper's overlap (Sec. 5.2) and noise (Sec. 5.3) studies.
+    """Synthetic analogue of the paper's overlap (Sec. 4.2) and noise (Sec. 4.3) studies.
 
     Object from textured_object, zone-plate probe, overlap raster, the perturbed initial probe
-    of Sec. 5.1; noiseless data, or Poisson data at a target Noise%.  alpha defaults to the
+    of Sec. 4.1; noiseless data, or Poisson data at a target Noise%.  alpha defaults to the
     paper's choice (0.05 at 50% overlap and for the noise study, 0.01 at 75% / 87.5%).
     """
     rng = np.random.default_rng(seed)

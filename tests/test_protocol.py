@@ -1,4 +1,4 @@
-"""Host logic of the experiment protocol (Sec. 5.1) and the protocol input generators."""
+"""Host logic of the experiment protocol (Sec. 4.1) and the protocol input generators."""
 import math
 
 import numpy as np
