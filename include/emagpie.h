@@ -4,7 +4,7 @@
  * (Zhang, Deng, Jiang, Di, "Stochastic Multigrid Method for Blind
  * Ptychographic Phase Retrieval", arXiv 2511.01793).
  *
- * Problem statement (Sec. 2.1): recover a complex object z (n x n) and a
+ * Problem statement (Sec. 2.1): recover a complex object z (n_rows x n_cols) and a
  * complex probe Q (m x m) from far-field intensities d_k = |F(Q . P_k z)|^2
  * measured at N scan positions, where P_k selects the m x m window whose
  * top-left corner is positions[k] and F is the unnormalised 2-D DFT.
@@ -20,8 +20,14 @@
  *    enqueued on it and is asynchronous unless stated otherwise.
  *  - Every call returns an emagpie_status; argument errors are detected on
  *    the host before anything is enqueued and leave all buffers untouched.
- *    emagpie_last_error() returns a message for the last failure on the
- *    calling thread.
+ *    emagpie_last_error(ctx) returns a message for the last failure of a
+ *    call on that context (NULL: the last failure on the calling thread).
+ *  - Device-side errors (a grid barrier of the persistent epoch that gave up
+ *    waiting) are raised by the kernel into host-visible memory and returned
+ *    as EMAGPIE_E_HIP by the first call on the context made after the failing
+ *    work has completed (synchronise the stream to be sure of seeing it);
+ *    that call does nothing else, and the state the failing epoch wrote is
+ *    not valid.
  *  - A context is not thread-safe; distinct contexts are independent.
  *  - Results are deterministic: the same inputs give bitwise-identical
  *    outputs (no floating-point atomics; every sum has a fixed order).
@@ -70,8 +76,9 @@ enum { EMAGPIE_TUNE = -1 };
 enum { EMAGPIE_F32 = 0, EMAGPIE_F64 = 1 };
 
 typedef struct {
-  int32_t n;            /* object side (square object, n x n)                       */
-  int32_t m;            /* probe side: 32, 64 or 128                                */
+  int32_t n_rows;       /* object rows (the object is n_rows x n_cols, row-major)   */
+  int32_t n_cols;       /* object columns; m <= n_rows, n_cols <= 65536            */
+  int32_t m;            /* probe side: 32, 64, 128 or 256                           */
   int32_t n_pos;        /* number of scan positions N >= 1                          */
   int32_t minibatch;    /* B >= 1 positions per update; B = 1 is the paper's
                            sequential sweep (Sec. 2.2, Sec. 3)                       */
@@ -122,8 +129,8 @@ emagpie_status emagpie_workspace_size(const emagpie_config* cfg, size_t* bytes);
 
 /*
  * Create a context.  positions_host: N x 2 int32 (row, col) top-left corners,
- * copied; every window must satisfy 0 <= row, col <= n - m (Sec. 2.1, binary
- * patch operator).  intensities_dev: N x m x m float32 measured intensities,
+ * copied; every window must satisfy 0 <= row <= n_rows - m and 0 <= col <=
+ * n_cols - m (Sec. 2.1, binary patch operator).  intensities_dev: N x m x m float32 measured intensities,
  * unshifted (zero frequency at [0, 0]); copied into the workspace, so the
  * caller may free it afterwards.  Negative counts act as zero amplitude
  * (a = sqrt(max(d, 0)), Def. 2.1).  workspace_dev must be 256-byte aligned
@@ -159,7 +166,7 @@ emagpie_status emagpie_normalize_probe(emagpie_ctx ctx, void* probe_dev, void* s
 
 /*
  * One eMAGPIE minibatch update (Sec. 3, Prop. 3.2 joint step, Sec. 3.2
- * multigrid object step), in place on obj_dev (n x n complex64) and
+ * multigrid object step), in place on obj_dev (n_rows x n_cols complex64) and
  * probe_dev (m x m complex64).  batch_idx_dev: b int32 scan indices in
  * [0, N) (distinct); all of them see the state at the start of the batch.
  * The object step minimises the summed regularised surrogates of the batch
@@ -225,7 +232,7 @@ emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* 
 
 /*
  * Gradients of Phi (Sec. 2.1, CR calculus; gradient = d/dx + i d/dy):
- * grad_obj = sum_k P_k^T conj(Q)(Q z_k - R_k) (n x n), grad_probe = sum_k
+ * grad_obj = sum_k P_k^T conj(Q)(Q z_k - R_k) (n_rows x n_cols), grad_probe = sum_k
  * conj(z_k)(Q z_k - R_k) (m x m), and Phi to misfit_dev.  dtype EMAGPIE_F32
  * takes complex64 obj/probe/gradients, EMAGPIE_F64 complex128 (m <= 64).
  * Gradients are overwritten, not accumulated.
@@ -304,8 +311,61 @@ emagpie_status emagpie_plan_get(emagpie_ctx ctx, emagpie_plan* out_host);
 emagpie_status emagpie_plan_describe(int32_t m, int32_t fft_plan, int32_t finalize_shape,
                                      emagpie_plan* out_host, int32_t* count_host);
 
-/* Message describing the last failure on the calling thread ("" if none). */
-const char* emagpie_last_error(void);
+/*
+ * Message describing the last failure of a call on ctx (a context of either
+ * kind; "" if none), or with ctx = NULL the last failure of any call on the
+ * calling thread (including calls that could not take a context: a failed
+ * init, workspace sizing, ...).  The string stays valid until the next call
+ * that fails on the same context / thread, or until the context is destroyed.
+ */
+const char* emagpie_last_error(emagpie_ctx ctx);
+
+/*
+ * Many independent reconstructions behind one context (batched instances,
+ * single-handle form of the group API above).  emagpie_init_many creates n_inst member
+ * contexts, each exactly as emagpie_init would from cfgs[i], positions_host[i]
+ * and intensities_dev[i] (each autotunes at init if its config asks to), plus a
+ * group of them, all inside one caller workspace of emagpie_workspace_size_many
+ * bytes (256-byte aligned; it must outlive the context).  emagpie_epoch_many is
+ * emagpie_group_epoch over the members: one sweep of every instance, bitwise the
+ * result of emagpie_epoch on each member alone.  obj_devs / probe_devs are host
+ * arrays of n_inst device pointers; sampled_misfit_dev (nullable) receives n_inst
+ * doubles.  emagpie_many_member returns member i (owned by the many-context: do
+ * not destroy it) for the per-instance calls (misfit, grad, normalize_probe,
+ * step, ...).  emagpie_destroy on the many-context releases members and group.
+ * Single-instance calls on the many-context itself return EMAGPIE_E_ARG.
+ */
+emagpie_status emagpie_workspace_size_many(int32_t n_inst, const emagpie_config* cfgs, size_t* bytes);
+emagpie_status emagpie_init_many(emagpie_ctx* out, int32_t n_inst, const emagpie_config* cfgs,
+                                 const int32_t* const* positions_host,
+                                 const float* const* intensities_dev, void* workspace_dev,
+                                 size_t workspace_bytes, void* stream);
+emagpie_status emagpie_epoch_many(emagpie_ctx ctx, void* const* obj_devs, void* const* probe_devs,
+                                  int64_t epoch, double* sampled_misfit_dev, void* stream);
+emagpie_status emagpie_many_member(emagpie_ctx ctx, int32_t i, emagpie_ctx* member_out);
+
+/*
+ * Fault-injection hook for the device-side error path of the persistent epoch
+ * (tests only).  Later persistent epochs of ctx poll each grid barrier at most
+ * spin_limit times (0 restores the default, 2^25) and wait for target_skew more
+ * arrivals than the grid makes, so with target_skew > 0 every barrier wait gives
+ * up after spin_limit polls: the kernel still runs to its end (its results are
+ * then not valid) and raises the device error that the next call returns.
+ * Host only.
+ */
+emagpie_status emagpie_debug_barrier(emagpie_ctx ctx, uint32_t spin_limit, uint32_t target_skew);
+
+/*
+ * Measured peaks for the roofline, on the caller's device buffer (bytes >=
+ * 4 MiB, 256-byte aligned): out2_host[0] = copy bandwidth in GB/s (a plain
+ * 16-byte-per-lane device copy from the first half of the buffer to the second;
+ * bytes read plus bytes written over the median kernel time of reps launches),
+ * out2_host[1] = FP32 vector rate in TFLOP/s (independent fused multiply-adds,
+ * 2 flops each, built like the method's kernels: packed FP32 forms disabled).
+ * Overwrites the buffer; synchronises the stream.
+ */
+emagpie_status emagpie_measure_peaks(void* buf_dev, size_t bytes, int32_t reps, double* out2_host,
+                                     void* stream);
 
 /* Library version string. */
 const char* emagpie_version(void);

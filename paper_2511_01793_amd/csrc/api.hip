@@ -15,10 +15,14 @@
 
 namespace {
 
+// The last failure on this thread, and a count of failures so far: an entry point
+// that takes a context copies a failure raised during the call into the context.
 thread_local std::string g_err;
+thread_local uint64_t g_err_count = 0;
 
 emagpie_status fail(emagpie_status st, const std::string& msg) {
   g_err = msg;
+  ++g_err_count;
   return st;
 }
 
@@ -81,6 +85,8 @@ struct Region {
   size_t off, bytes;
 };
 
+constexpr unsigned kDefaultSpinLimit = 1u << 25;
+
 bool wants_tuning(const emagpie_config& c) {
   return c.fft_plan == EMAGPIE_TUNE || c.finalize_shape == EMAGPIE_TUNE || c.path == EMAGPIE_PATH_AUTO;
 }
@@ -126,7 +132,7 @@ Layout make_layout(const emagpie_config& c) {
   L.gq = take((size_t)L.grad_chunk * m2 * gel);
   // scratch state for autotuning at init (only when asked for)
   const bool tune = wants_tuning(c);
-  L.tune_obj = take(tune ? (size_t)c.n * c.n * 8 : 0);
+  L.tune_obj = take(tune ? (size_t)c.n_rows * c.n_cols * 8 : 0);
   L.tune_probe = take(tune ? m2 * 8 : 0);
   L.phase = take(c.zero_phase_memory ? N * m2 * 8 : 0);
   // m = 256: strip maxima and column-block partial misfits per slot (16 of each)
@@ -139,7 +145,10 @@ emagpie_status check_config(const emagpie_config* c) {
   if (!c) return fail(EMAGPIE_E_ARG, "null config");
   if (c->m != 32 && c->m != 64 && c->m != 128 && c->m != 256)
     return fail(EMAGPIE_E_SHAPE, "probe side m must be 32, 64, 128 or 256");
-  if (c->n < c->m || c->n > 65536) return fail(EMAGPIE_E_SHAPE, "object side n must satisfy m <= n <= 65536");
+  if (c->n_rows < c->m || c->n_rows > 65536 || c->n_cols < c->m || c->n_cols > 65536)
+    return fail(EMAGPIE_E_SHAPE, "object sides must satisfy m <= n_rows, n_cols <= 65536");
+  if ((size_t)c->n_rows * (size_t)c->n_cols > (size_t)1 << 31)
+    return fail(EMAGPIE_E_SHAPE, "object larger than 2^31 pixels");
   if (c->n_pos < 1) return fail(EMAGPIE_E_SHAPE, "n_pos must be >= 1");
   if (c->minibatch < 1 || c->minibatch > emg::kMaxSlots)
     return fail(EMAGPIE_E_SHAPE, "minibatch must be in [1, 1024]");
@@ -167,6 +176,8 @@ emagpie_status check_config(const emagpie_config* c) {
 }
 
 }  // namespace
+
+struct Many;  // members and group of a context made by emagpie_init_many
 
 struct emagpie_ctx_s {
   emagpie_config cfg;  // path, fft_plan and finalize_shape hold the resolved choice
@@ -209,14 +220,61 @@ struct emagpie_ctx_s {
   bool profile = false;
   std::vector<hipEvent_t> ev[3];
   size_t ev_used[3] = {0, 0, 0};
+  // device-side error flag in host memory (fine-grained, mapped): a persistent
+  // epoch's grid barrier that gave up waiting sets it; the next call reports it
+  int* dev_err_host = nullptr;
+  int* dev_err_dev = nullptr;
+  unsigned spin_limit = kDefaultSpinLimit;
+  unsigned bar_skew = 0;  // extra arrivals awaited (fault injection; 0 in normal use)
+  std::string err;        // last failure of a call on this context
+  // a context made by emagpie_init_many: its members and their group
+  Many* many = nullptr;
 };
 
 namespace {
 
+#define EMG_OK(expr)                      \
+  do {                                    \
+    emagpie_status st_ = (expr);          \
+    if (st_ != EMAGPIE_OK) return st_;    \
+  } while (0)
+
+// Copies a failure raised during an entry point's call into its context (the
+// message emagpie_last_error(ctx) returns).
+struct CtxErrScope {
+  emagpie_ctx c;
+  uint64_t n0;
+  explicit CtxErrScope(emagpie_ctx c_) : c(c_), n0(g_err_count) {}
+  ~CtxErrScope() {
+    if (c && g_err_count != n0) c->err = g_err;
+  }
+};
+
+// Entry check of a call on a single-instance context: not null, not a
+// many-context, and no device error pending from earlier work.  A pending error is
+// returned (once) instead of doing the call; the persistent barrier counter is then
+// re-zeroed before the next persistent epoch.
+emagpie_status use_ctx(emagpie_ctx c) {
+  if (!c) return fail(EMAGPIE_E_ARG, "null context");
+  if (c->many)
+    return fail(EMAGPIE_E_ARG, "a context made by emagpie_init_many takes emagpie_epoch_many; "
+                               "use emagpie_many_member for per-instance calls");
+  if (c->dev_err_host && __atomic_load_n(c->dev_err_host, __ATOMIC_ACQUIRE) != 0) {
+    __atomic_store_n(c->dev_err_host, 0, __ATOMIC_RELEASE);
+    c->bar_ready = false;
+    return fail(EMAGPIE_E_HIP,
+                "device error raised by earlier work on this context: a grid barrier of a persistent "
+                "epoch gave up waiting for the other workgroups; the object and probe that epoch "
+                "wrote are not valid");
+  }
+  return EMAGPIE_OK;
+}
+
 emg::StepArgs base_args(emagpie_ctx c, void* obj, void* probe) {
   emg::StepArgs a{};
   a.obj = static_cast<float2*>(obj);
-  a.n = c->cfg.n;
+  a.n = c->cfg.n_cols;
+  a.nr = c->cfg.n_rows;
   a.probe = static_cast<float2*>(probe);
   a.dperm = c->dperm;
   a.pos = c->pos;
@@ -262,12 +320,6 @@ emagpie_status take_pair(emagpie_ctx c, int cat, bool instrument, hipEvent_t* e0
   *e1 = c->ev[cat][c->ev_used[cat]++];
   return EMAGPIE_OK;
 }
-
-#define EMG_OK(expr)                      \
-  do {                                    \
-    emagpie_status st_ = (expr);          \
-    if (st_ != EMAGPIE_OK) return st_;    \
-  } while (0)
 
 // enqueue one minibatch with the configured (non-graph) strategy
 emagpie_status enqueue_minibatch(emagpie_ctx c, const emg::StepArgs& a, bool plain, hipStream_t s,
@@ -341,9 +393,9 @@ std::string tune_key(emagpie_ctx c, const emagpie_config& req) {
   const emagpie_config& k = c->cfg;
   char buf[512];
   std::snprintf(buf, sizeof buf,
-                "%s cus=%d m=%d n=%d N=%d B=%d L=%d blind=%d joint=%d az1=%d mem=%d plan=%d shape=%d "
-                "path=%d",
-                arch.c_str(), c->num_cus, k.m, k.n, k.n_pos, k.minibatch, k.levels, k.update_probe,
+                "%s cus=%d m=%d n=%dx%d N=%d B=%d L=%d blind=%d joint=%d az1=%d mem=%d plan=%d "
+                "shape=%d path=%d",
+                arch.c_str(), c->num_cus, k.m, k.n_rows, k.n_cols, k.n_pos, k.minibatch, k.levels, k.update_probe,
                 k.joint_step, k.alpha_z == 1.0f ? 1 : 0, k.zero_phase_memory, req.fft_plan,
                 req.finalize_shape, req.path);
   return buf;
@@ -470,7 +522,7 @@ emagpie_status autotune(emagpie_ctx c, const emagpie_config& req, const float* i
   // scratch state (unit object, unit probe) and the epoch-0 scan order
   float2* tobj = reinterpret_cast<float2*>(c->ws + c->lay.tune_obj.off);
   float2* tprobe = reinterpret_cast<float2*>(c->ws + c->lay.tune_probe.off);
-  EMG_HIP(emg::launch_fill_c64(tobj, (size_t)c->cfg.n * c->cfg.n, make_float2(1.f, 0.f), s));
+  EMG_HIP(emg::launch_fill_c64(tobj, (size_t)c->cfg.n_rows * c->cfg.n_cols, make_float2(1.f, 0.f), s));
   EMG_HIP(emg::launch_fill_c64(tprobe, (size_t)m * m, make_float2(1.f, 0.f), s));
   std::vector<int32_t> perm(N);
   fisher_yates(c->cfg.seed, 0, N, perm.data());
@@ -589,7 +641,7 @@ extern "C" {
 
 const char* emagpie_version(void) { return "libemagpie 0.1 (gfx950)"; }
 
-const char* emagpie_last_error(void) { return g_err.c_str(); }
+const char* emagpie_last_error(emagpie_ctx ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
 emagpie_status emagpie_workspace_size(const emagpie_config* cfg, size_t* bytes) {
   emagpie_status st = check_config(cfg);
@@ -616,7 +668,7 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   const emagpie_config c = *cfg;
   for (int k = 0; k < c.n_pos; ++k) {
     const int32_t r = positions_host[2 * k], q = positions_host[2 * k + 1];
-    if (r < 0 || q < 0 || r > c.n - c.m || q > c.n - c.m)
+    if (r < 0 || q < 0 || r > c.n_rows - c.m || q > c.n_cols - c.m)
       return fail(EMAGPIE_E_POSITION, "scan position " + std::to_string(k) + " = (" +
                                           std::to_string(r) + ", " + std::to_string(q) +
                                           ") leaves the object");
@@ -730,6 +782,15 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
     if ((e = hipEventCreateWithFlags(&ctx->perm_ev[i], hipEventDisableTiming)) != hipSuccess)
       return hipfail(e, "event");
   }
+  // the device-side error flag: fine-grained host memory the kernels can write and
+  // the host can read at its next call without synchronising
+  if ((e = hipHostMalloc(reinterpret_cast<void**>(&ctx->dev_err_host), 64,
+                         hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
+    return hipfail(e, "device error flag");
+  __atomic_store_n(ctx->dev_err_host, 0, __ATOMIC_RELEASE);
+  if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->dev_err_dev), ctx->dev_err_host, 0)) !=
+      hipSuccess)
+    return hipfail(e, "device error flag mapping");
   fill_plan_info(ctx, 0);
   if (wants_tuning(c)) {
     emagpie_status ts = autotune(ctx, c, intensities_dev, s);
@@ -742,7 +803,8 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
 }
 
 emagpie_status emagpie_phase_memory_reset(emagpie_ctx ctx, void* stream) {
-  if (!ctx) return fail(EMAGPIE_E_ARG, "null context");
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
   if (!ctx->phase) return fail(EMAGPIE_E_ARG, "the context has no phase memory");
   EMG_HIP(emg::launch_fill_c64(ctx->phase, (size_t)ctx->cfg.n_pos * ctx->cfg.m * ctx->cfg.m,
                                make_float2(1.f, 0.f), static_cast<hipStream_t>(stream)));
@@ -750,7 +812,9 @@ emagpie_status emagpie_phase_memory_reset(emagpie_ctx ctx, void* stream) {
 }
 
 emagpie_status emagpie_plan_get(emagpie_ctx ctx, emagpie_plan* out_host) {
-  if (!ctx || !out_host) return fail(EMAGPIE_E_ARG, "null argument");
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!out_host) return fail(EMAGPIE_E_ARG, "null argument");
   *out_host = ctx->plan;
   return EMAGPIE_OK;
 }
@@ -773,13 +837,16 @@ emagpie_status emagpie_plan_describe(int32_t m, int32_t fft_plan, int32_t finali
 }
 
 emagpie_status emagpie_profile_enable(emagpie_ctx ctx, int32_t enable) {
-  if (!ctx) return fail(EMAGPIE_E_ARG, "null context");
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
   ctx->profile = enable != 0;
   return EMAGPIE_OK;
 }
 
 emagpie_status emagpie_profile_read(emagpie_ctx ctx, double* ms3_host, int64_t* count3_host) {
-  if (!ctx || !ms3_host || !count3_host) return fail(EMAGPIE_E_ARG, "null argument");
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!ms3_host || !count3_host) return fail(EMAGPIE_E_ARG, "null argument");
   for (int cat = 0; cat < 3; ++cat) {
     double tot = 0.0;
     const size_t used = ctx->ev_used[cat];
@@ -796,8 +863,14 @@ emagpie_status emagpie_profile_read(emagpie_ctx ctx, double* ms3_host, int64_t* 
   return EMAGPIE_OK;
 }
 
+void destroy_many(emagpie_ctx ctx);
+
 emagpie_status emagpie_destroy(emagpie_ctx ctx) {
   if (!ctx) return EMAGPIE_OK;
+  if (ctx->many) {
+    destroy_many(ctx);
+    return EMAGPIE_OK;
+  }
   drop_graph(ctx);
   for (int cat = 0; cat < 3; ++cat) {
     for (hipEvent_t e : ctx->ev[cat]) {
@@ -813,18 +886,23 @@ emagpie_status emagpie_destroy(emagpie_ctx ctx) {
     }
     if (ctx->perm_pinned[i]) (void)hipHostFree(ctx->perm_pinned[i]);
   }
+  if (ctx->dev_err_host) (void)hipHostFree(ctx->dev_err_host);
   delete ctx;
   return EMAGPIE_OK;
 }
 
 emagpie_status emagpie_dp_avg(emagpie_ctx ctx, double* dp_avg_host) {
-  if (!ctx || !dp_avg_host) return fail(EMAGPIE_E_ARG, "null argument");
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!dp_avg_host) return fail(EMAGPIE_E_ARG, "null argument");
   *dp_avg_host = ctx->dp_avg;
   return EMAGPIE_OK;
 }
 
 emagpie_status emagpie_normalize_probe(emagpie_ctx ctx, void* probe_dev, void* stream) {
-  if (!ctx || !probe_dev) return fail(EMAGPIE_E_ARG, "null argument");
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!probe_dev) return fail(EMAGPIE_E_ARG, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int flag = 0;
   EMG_HIP(hipMemsetAsync(ctx->scal_i + 1, 0, sizeof(int), s));
@@ -839,7 +917,9 @@ emagpie_status emagpie_normalize_probe(emagpie_ctx ctx, void* probe_dev, void* s
 emagpie_status emagpie_step_minibatch(emagpie_ctx ctx, void* obj_dev, void* probe_dev,
                                       const int32_t* batch_idx_dev, int32_t b,
                                       double* sampled_misfit_dev, void* stream) {
-  if (!ctx || !obj_dev || !probe_dev || !batch_idx_dev) return fail(EMAGPIE_E_ARG, "null argument");
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!obj_dev || !probe_dev || !batch_idx_dev) return fail(EMAGPIE_E_ARG, "null argument");
   if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
   hipStream_t s = static_cast<hipStream_t>(stream);
   EMG_HIP(emg::launch_slot_info(batch_idx_dev, ctx->pos, ctx->cfg.n_pos, ctx->slots, b, s));
@@ -857,7 +937,9 @@ emagpie_status emagpie_step_minibatch(emagpie_ctx ctx, void* obj_dev, void* prob
 
 emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, int64_t epoch,
                              const int32_t* perm_dev, double* sampled_misfit_dev, void* stream) {
-  if (!ctx || !obj_dev || !probe_dev) return fail(EMAGPIE_E_ARG, "null argument");
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!obj_dev || !probe_dev) return fail(EMAGPIE_E_ARG, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int N = ctx->cfg.n_pos;
   if (perm_dev) {
@@ -937,9 +1019,11 @@ emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, in
       if (e0) EMG_HIP(hipEventRecord(e0, s));
       EMG_HIP(emg::launch_persistent_epoch(ctx->cfg.m, ctx->cfg.fft_plan, ctx->cfg.levels, a, N,
                                            ctx->cfg.minibatch,
-                                           ctx->persist_grid, ctx->bar, ctx->bar_base,
-                                           ctx->scal_i + 2, &used, s));
+                                           ctx->persist_grid, ctx->bar, ctx->bar_base + ctx->bar_skew,
+                                           ctx->dev_err_dev, ctx->spin_limit, &used, s));
       if (e1) EMG_HIP(hipEventRecord(e1, s));
+      // every workgroup arrives once at each of the 2 barriers of each minibatch, also
+      // when a wait gives up (the device error then re-zeroes the counter first)
       const unsigned nbatch = (unsigned)((N + ctx->cfg.minibatch - 1) / ctx->cfg.minibatch);
       ctx->bar_base += 2u * nbatch * (unsigned)used;
       return EMAGPIE_OK;
@@ -952,7 +1036,9 @@ emagpie_status emagpie_epoch(emagpie_ctx ctx, void* obj_dev, void* probe_dev, in
 emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
                                 const int32_t* batch_idx_dev, int32_t b, void* zplus_dev,
                                 void* stream) {
-  if (!ctx || !obj_dev || !probe_dev || !batch_idx_dev || !zplus_dev)
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!obj_dev || !probe_dev || !batch_idx_dev || !zplus_dev)
     return fail(EMAGPIE_E_ARG, "null argument");
   if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -970,7 +1056,9 @@ emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void
 emagpie_status emagpie_check_step(emagpie_ctx ctx, void* obj_dev, void* probe_dev,
                                   const int32_t* batch_idx_dev, int32_t b, double* out3_dev,
                                   void* stream) {
-  if (!ctx || !obj_dev || !probe_dev || !batch_idx_dev || !out3_dev)
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!obj_dev || !probe_dev || !batch_idx_dev || !out3_dev)
     return fail(EMAGPIE_E_ARG, "null argument");
   if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
   if (ctx->cfg.m == 256) return fail(EMAGPIE_E_UNSUPPORTED, "no descent check for m = 256");
@@ -989,7 +1077,7 @@ emagpie_status emagpie_check_step(emagpie_ctx ctx, void* obj_dev, void* probe_de
   // [1] surrogate of Eq. 3 at the new state against the frozen R_k, [2] Phi_B at the new state
   EMG_HIP(emg::launch_surrogate_terms(m, v, a, ctx->phi, s));
   EMG_HIP(emg::launch_sum_doubles(ctx->phi, b, out3_dev + 1, s));
-  EMG_HIP(emg::launch_misfit_terms(m, v, static_cast<const float2*>(obj_dev), ctx->cfg.n,
+  EMG_HIP(emg::launch_misfit_terms(m, v, static_cast<const float2*>(obj_dev), ctx->cfg.n_cols,
                                    static_cast<const float2*>(probe_dev), ctx->dperm, ctx->pos,
                                    ctx->slots, b, ctx->tw32, ctx->phi, s));
   EMG_HIP(emg::launch_sum_doubles(ctx->phi, b, out3_dev + 2, s));
@@ -998,7 +1086,9 @@ emagpie_status emagpie_check_step(emagpie_ctx ctx, void* obj_dev, void* probe_de
 
 emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
                               double* misfit_dev, void* stream) {
-  if (!ctx || !obj_dev || !probe_dev || !misfit_dev) return fail(EMAGPIE_E_ARG, "null argument");
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!obj_dev || !probe_dev || !misfit_dev) return fail(EMAGPIE_E_ARG, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (ctx->cfg.m == 256) {
     // strips and column blocks over the stack buffer, minibatch-sized chunks of patterns
@@ -1011,7 +1101,7 @@ emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* 
     return EMAGPIE_OK;
   }
   EMG_HIP(emg::launch_misfit_terms(ctx->cfg.m, ctx->cfg.fft_plan, static_cast<const float2*>(obj_dev),
-                                   ctx->cfg.n, static_cast<const float2*>(probe_dev), ctx->dperm,
+                                   ctx->cfg.n_cols, static_cast<const float2*>(probe_dev), ctx->dperm,
                                    ctx->pos, nullptr, ctx->cfg.n_pos, ctx->tw32, ctx->phi_all, s));
   EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
   return EMAGPIE_OK;
@@ -1020,7 +1110,9 @@ emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* 
 emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
                             void* grad_obj_dev, void* grad_probe_dev, double* misfit_dev,
                             int32_t dtype, void* stream) {
-  if (!ctx || !obj_dev || !probe_dev || !grad_obj_dev || !grad_probe_dev)
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  if (!obj_dev || !probe_dev || !grad_obj_dev || !grad_probe_dev)
     return fail(EMAGPIE_E_ARG, "null argument");
   if (dtype != EMAGPIE_F32 && dtype != EMAGPIE_F64) return fail(EMAGPIE_E_ARG, "dtype must be F32 or F64");
   const bool f64 = dtype == EMAGPIE_F64;
@@ -1029,7 +1121,8 @@ emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* pr
   hipStream_t s = static_cast<hipStream_t>(stream);
   emg::GradArgs g{};
   g.obj = obj_dev;
-  g.n = ctx->cfg.n;
+  g.n = ctx->cfg.n_cols;
+  g.nr = ctx->cfg.n_rows;
   g.probe = probe_dev;
   g.dperm = ctx->dperm;
   g.pos = ctx->pos;
@@ -1068,24 +1161,25 @@ struct GroupLayout {
   std::vector<int2> work_host;  // all work lists, concatenated
 };
 
-emagpie_status plan_group(int32_t n_inst, const emagpie_ctx* ctxs, GroupLayout* G) {
-  if (n_inst < 1 || !ctxs) return fail(EMAGPIE_E_ARG, "a group needs at least one context");
+// Per-step work lists of a group of configurations (each resolved, or with
+// finalize_shape = EMAGPIE_TUNE when only the size is wanted: the shape with the
+// most work items then stands in, so the size is an upper bound).
+emagpie_status plan_group_cfgs(const std::vector<emagpie_config>& cfgs, GroupLayout* G) {
+  const int n_inst = (int)cfgs.size();
+  if (n_inst < 1) return fail(EMAGPIE_E_ARG, "a group needs at least one instance");
   G->steps = 0;
   G->slot_off.assign(n_inst, 0);
   size_t nslots = 0;
   for (int i = 0; i < n_inst; ++i) {
-    if (!ctxs[i]) return fail(EMAGPIE_E_ARG, "null context in group");
-    if (ctxs[i]->cfg.m == 256) return fail(EMAGPIE_E_UNSUPPORTED, "group members need m <= 128");
-    for (int j = 0; j < i; ++j)
-      if (ctxs[j] == ctxs[i]) return fail(EMAGPIE_E_ARG, "a context appears twice in the group");
-    const emagpie_config& c = ctxs[i]->cfg;
+    const emagpie_config& c = cfgs[i];
+    if (c.m == 256) return fail(EMAGPIE_E_UNSUPPORTED, "group members need m <= 128");
     G->slot_off[i] = nslots;
     nslots += (size_t)c.n_pos;
     G->steps = std::max(G->steps, (c.n_pos + c.minibatch - 1) / c.minibatch);
   }
   G->classes.clear();
   for (int i = 0; i < n_inst; ++i) {
-    const emagpie_config& c = ctxs[i]->cfg;
+    const emagpie_config& c = cfgs[i];
     GroupClass* cls = nullptr;
     for (auto& k : G->classes)
       if (k.m == c.m && k.L == c.levels && k.v == c.fft_plan && k.f == c.finalize_shape) cls = &k;
@@ -1100,19 +1194,24 @@ emagpie_status plan_group(int32_t n_inst, const emagpie_ctx* ctxs, GroupLayout* 
     for (int j = 0; j < G->steps; ++j) {
       k.patch_off.push_back(G->work_host.size());
       for (int i : k.inst) {
-        const emagpie_config& c = ctxs[i]->cfg;
+        const emagpie_config& c = cfgs[i];
         const int b = std::min(c.minibatch, c.n_pos - j * c.minibatch);
         for (int s = 0; s < b; ++s) G->work_host.push_back(make_int2(j * n_inst + i, s));
       }
       k.patch_n.push_back((int)(G->work_host.size() - k.patch_off.back()));
       k.fin_off.push_back(G->work_host.size());
       for (int i : k.inst) {
-        const emagpie_config& c = ctxs[i]->cfg;
+        const emagpie_config& c = cfgs[i];
         if (j * c.minibatch >= c.n_pos) continue;
         int items = 0;
-        if (emg::finalize_item_count(c.m, c.finalize_shape, c.n, emg::probe_groups(c.minibatch),
-                                     &items) != hipSuccess)
-          return fail(EMAGPIE_E_SHAPE, "unsupported probe size in group");
+        for (int f = 0; f < emg::kFinShapes; ++f) {
+          if (c.finalize_shape != EMAGPIE_TUNE && f != c.finalize_shape) continue;
+          int it = 0;
+          if (emg::finalize_item_count(c.m, f, c.n_rows, c.n_cols, emg::probe_groups(c.minibatch),
+                                       &it) != hipSuccess)
+            return fail(EMAGPIE_E_SHAPE, "unsupported probe size in group");
+          items = std::max(items, it);
+        }
         for (int t = 0; t < items; ++t) G->work_host.push_back(make_int2(j * n_inst + i, t));
       }
       k.fin_n.push_back((int)(G->work_host.size() - k.fin_off.back()));
@@ -1129,6 +1228,19 @@ emagpie_status plan_group(int32_t n_inst, const emagpie_ctx* ctxs, GroupLayout* 
   G->work = take(G->work_host.size() * sizeof(int2));
   G->total = cur;
   return EMAGPIE_OK;
+}
+
+emagpie_status plan_group(int32_t n_inst, const emagpie_ctx* ctxs, GroupLayout* G) {
+  if (n_inst < 1 || !ctxs) return fail(EMAGPIE_E_ARG, "a group needs at least one context");
+  std::vector<emagpie_config> cfgs(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    if (!ctxs[i]) return fail(EMAGPIE_E_ARG, "null context in group");
+    if (ctxs[i]->many) return fail(EMAGPIE_E_ARG, "a many-context cannot be a group member");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(EMAGPIE_E_ARG, "a context appears twice in the group");
+    cfgs[i] = ctxs[i]->cfg;
+  }
+  return plan_group_cfgs(cfgs, G);
 }
 
 }  // namespace
@@ -1319,6 +1431,176 @@ emagpie_status emagpie_group_epoch(emagpie_group g, void* const* obj_devs, void*
     EMG_HIP(hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0));
   }
   EMG_HIP(hipGraphLaunch(g->gexec, s));
+  return EMAGPIE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// many instances behind one context, fault injection, measured peaks
+// ---------------------------------------------------------------------------
+struct Many {
+  std::vector<emagpie_ctx> members;
+  emagpie_group group = nullptr;
+};
+
+namespace {
+
+// member workspaces (256-byte aligned, in order), then the group workspace
+struct ManyLayout {
+  std::vector<size_t> off, bytes;
+  size_t group_off = 0, group_bytes = 0, total = 0;
+};
+
+emagpie_status many_layout(int32_t n_inst, const emagpie_config* cfgs, ManyLayout* M) {
+  if (n_inst < 1 || !cfgs) return fail(EMAGPIE_E_ARG, "emagpie_init_many needs at least one configuration");
+  size_t cur = 0;
+  std::vector<emagpie_config> v(cfgs, cfgs + n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    emagpie_status st = check_config(&cfgs[i]);
+    if (st != EMAGPIE_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+    const size_t b = make_layout(cfgs[i]).total;
+    M->off.push_back(cur);
+    M->bytes.push_back(b);
+    cur += align256(b);
+  }
+  GroupLayout G;
+  EMG_OK(plan_group_cfgs(v, &G));
+  M->group_off = cur;
+  M->group_bytes = G.total;
+  M->total = cur + align256(G.total);
+  return EMAGPIE_OK;
+}
+
+}  // namespace
+
+void destroy_many(emagpie_ctx ctx) {
+  Many* mm = ctx->many;
+  if (mm->group) (void)emagpie_group_destroy(mm->group);
+  for (emagpie_ctx c : mm->members) (void)emagpie_destroy(c);
+  delete mm;
+  delete ctx;
+}
+
+extern "C" {
+
+emagpie_status emagpie_workspace_size_many(int32_t n_inst, const emagpie_config* cfgs, size_t* bytes) {
+  if (!bytes) return fail(EMAGPIE_E_ARG, "null output");
+  ManyLayout M;
+  EMG_OK(many_layout(n_inst, cfgs, &M));
+  *bytes = M.total;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_init_many(emagpie_ctx* out, int32_t n_inst, const emagpie_config* cfgs,
+                                 const int32_t* const* positions_host,
+                                 const float* const* intensities_dev, void* workspace_dev,
+                                 size_t workspace_bytes, void* stream) {
+  if (!out) return fail(EMAGPIE_E_ARG, "null context output");
+  *out = nullptr;
+  if (!positions_host || !intensities_dev) return fail(EMAGPIE_E_ARG, "null positions or intensities array");
+  ManyLayout M;
+  EMG_OK(many_layout(n_inst, cfgs, &M));
+  if (!workspace_dev || (reinterpret_cast<uintptr_t>(workspace_dev) & 255))
+    return fail(EMAGPIE_E_WORKSPACE, "workspace missing or not 256-byte aligned");
+  if (workspace_bytes < M.total)
+    return fail(EMAGPIE_E_WORKSPACE, "workspace too small: need " + std::to_string(M.total) +
+                                         " bytes, got " + std::to_string(workspace_bytes));
+  uint8_t* w = static_cast<uint8_t*>(workspace_dev);
+  auto* mm = new Many();
+  auto* ctx = new emagpie_ctx_s();
+  ctx->cfg = cfgs[0];
+  ctx->many = mm;
+  for (int i = 0; i < n_inst; ++i) {
+    emagpie_ctx c = nullptr;
+    emagpie_status st = emagpie_init(&c, &cfgs[i], positions_host[i], intensities_dev[i], w + M.off[i],
+                                     M.bytes[i], stream);
+    if (st != EMAGPIE_OK) {
+      const std::string msg = "instance " + std::to_string(i) + ": " + g_err;
+      destroy_many(ctx);
+      return fail(st, msg);
+    }
+    mm->members.push_back(c);
+  }
+  emagpie_status st = emagpie_group_create(&mm->group, n_inst, mm->members.data(), w + M.group_off,
+                                           M.group_bytes, stream);
+  if (st != EMAGPIE_OK) {
+    const std::string msg = g_err;
+    destroy_many(ctx);
+    return fail(st, msg);
+  }
+  *out = ctx;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_epoch_many(emagpie_ctx ctx, void* const* obj_devs, void* const* probe_devs,
+                                  int64_t epoch, double* sampled_misfit_dev, void* stream) {
+  CtxErrScope es_(ctx);
+  if (!ctx || !ctx->many) return fail(EMAGPIE_E_ARG, "not a context made by emagpie_init_many");
+  for (emagpie_ctx c : ctx->many->members) EMG_OK(use_ctx(c));
+  return emagpie_group_epoch(ctx->many->group, obj_devs, probe_devs, epoch, sampled_misfit_dev, stream);
+}
+
+emagpie_status emagpie_many_member(emagpie_ctx ctx, int32_t i, emagpie_ctx* member_out) {
+  CtxErrScope es_(ctx);
+  if (!ctx || !ctx->many || !member_out) return fail(EMAGPIE_E_ARG, "null argument or not a many-context");
+  if (i < 0 || i >= (int)ctx->many->members.size()) return fail(EMAGPIE_E_ARG, "member index out of range");
+  *member_out = ctx->many->members[i];
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_debug_barrier(emagpie_ctx ctx, uint32_t spin_limit, uint32_t target_skew) {
+  CtxErrScope es_(ctx);
+  EMG_OK(use_ctx(ctx));
+  ctx->spin_limit = spin_limit ? spin_limit : kDefaultSpinLimit;
+  ctx->bar_skew = target_skew;
+  return EMAGPIE_OK;
+}
+
+emagpie_status emagpie_measure_peaks(void* buf_dev, size_t bytes, int32_t reps, double* out2_host,
+                                     void* stream) {
+  if (!buf_dev || !out2_host || reps < 1) return fail(EMAGPIE_E_ARG, "null buffer or output, or reps < 1");
+  if ((reinterpret_cast<uintptr_t>(buf_dev) & 255) || bytes < (size_t(4) << 20))
+    return fail(EMAGPIE_E_WORKSPACE, "buffer must be 256-byte aligned and at least 4 MiB");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0, cus = 0;
+  EMG_HIP(hipGetDevice(&dev));
+  EMG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const size_t n4 = bytes / 2 / 16;
+  uint8_t* b = static_cast<uint8_t*>(buf_dev);
+  const int copy_blocks = 16 * cus, fma_blocks = 8 * cus, fma_iters = 4096;
+  if ((size_t)fma_blocks * 256 * sizeof(float) > bytes)
+    return fail(EMAGPIE_E_WORKSPACE, "buffer too small for the FMA loop's output");
+  double flops = 0.0;
+  std::vector<float> t_copy, t_fma;
+  std::vector<hipEvent_t> ev(2 * reps, nullptr);
+  emagpie_status st = EMAGPIE_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) st = fail(EMAGPIE_E_HIP, "peak-measurement event");
+  for (int pass = 0; st == EMAGPIE_OK && pass < 2; ++pass) {
+    // one untimed launch, then reps timed ones
+    for (int i = -1; st == EMAGPIE_OK && i < reps; ++i) {
+      if (i >= 0 && hipEventRecord(ev[2 * i], s) != hipSuccess) st = fail(EMAGPIE_E_HIP, "event record");
+      const hipError_t e = pass == 0 ? emg::launch_copy16(b, b + n4 * 16, n4, copy_blocks, s)
+                                     : emg::launch_fma_loop(reinterpret_cast<float*>(b), fma_blocks,
+                                                            fma_iters, s, &flops);
+      if (e != hipSuccess) st = fail(EMAGPIE_E_HIP, std::string("peak kernel: ") + hipGetErrorString(e));
+      if (st == EMAGPIE_OK && i >= 0 && hipEventRecord(ev[2 * i + 1], s) != hipSuccess)
+        st = fail(EMAGPIE_E_HIP, "event record");
+    }
+    if (st == EMAGPIE_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(EMAGPIE_E_HIP, "synchronise");
+    for (int i = 0; st == EMAGPIE_OK && i < reps; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess) st = fail(EMAGPIE_E_HIP, "timing");
+      (pass == 0 ? t_copy : t_fma).push_back(ms);
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (st != EMAGPIE_OK) return st;
+  out2_host[0] = 2.0 * (double)n4 * 16.0 / (median(t_copy) * 1e-3) / 1e9;
+  out2_host[1] = flops / (median(t_fma) * 1e-3) / 1e12;
   return EMAGPIE_OK;
 }
 

@@ -646,12 +646,13 @@ struct FinLds {
 };
 
 // object tiles, then probe units of FNT / G pixels (G slot groups per pixel)
+// over an nr x nc object (tile rows of ceil(nc / T) tiles)
 template <int M, int FNT, int T>
-__host__ __device__ inline int finalize_items(int n, int G, int* ntiles_out) {
-  const int tpr = (n + T - 1) / T;
+__host__ __device__ inline int finalize_items(int nr, int nc, int G, int* ntiles_out) {
+  const int tiles = ((nr + T - 1) / T) * ((nc + T - 1) / T);
   const int ppu = FNT / G;
-  *ntiles_out = tpr * tpr;
-  return tpr * tpr + (M * M + ppu - 1) / ppu;
+  *ntiles_out = tiles;
+  return tiles + (M * M + ppu - 1) / ppu;
 }
 
 // an empty register barrier: v is taken as written here, so later uses do not
@@ -676,7 +677,7 @@ template <int M, int FNT, int T>
 __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int ntiles, FinLds& L,
                                               int tid) {
   constexpr int PER = Fin<FNT, T>::PER;
-  const int n = a.n;
+  const int n = a.n, nr = a.nr;  // row stride (columns) and rows of the object
   if (item < ntiles) {
     const int tpr = (n + T - 1) / T;
     const int ty = (item / tpr) * T, tx = (item % tpr) * T;
@@ -687,7 +688,7 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
     for (int e = 0; e < PER; ++e) {
       const int q = tid + e * FNT;
       const int y = ty + q / T, x = tx + q % T;
-      zold[e] = (a.joint && y < n && x < n) ? ld(a.obj, (size_t)y * n + x) : cx<float>{0.f, 0.f};
+      zold[e] = (a.joint && y < nr && x < n) ? ld(a.obj, (size_t)y * n + x) : cx<float>{0.f, 0.f};
     }
     // Each wave scans the slots itself, 256 at a time (four loads of 64 issued
     // together): a ballot per 64 marks the ones whose window overlaps the tile, and
@@ -769,7 +770,7 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
     for (int e = 0; e < PER; ++e) {
       const int q = tid + e * FNT;
       const int y = ty + q / T, x = tx + q % T;
-      if (accd[e] > 0.f && y < n && x < n) {
+      if (accd[e] > 0.f && y < nr && x < n) {
         const size_t o = (size_t)y * n + x;
         const cx<float> zp = scale(accn[e], 1.f / accd[e]);
         st(a.obj, o, a.joint ? aligned_sqrt(zold[e], zp) : zp);
@@ -928,7 +929,7 @@ __global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize_multi(const StepA
   const int2 w = work[blockIdx.x];
   const StepArgs a = args[w.x];
   int ntiles;
-  finalize_items<M, FNT, T>(a.n, a.pgroups, &ntiles);
+  finalize_items<M, FNT, T>(a.nr, a.n, a.pgroups, &ntiles);
   finalize_item<M, FNT, T>(a, w.y, ntiles, L, tid);
 }
 
@@ -937,9 +938,12 @@ __global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize_multi(const StepA
 // reached L2; then one lane per workgroup releases at agent scope (L2
 // write-back, so other XCDs see the data), arrives on a monotonic counter,
 // waits for the target and acquires (stale lines dropped from this CU's L1 and
-// this XCD's L2) before the workgroup proceeds.  A bounded spin turns a lost
-// arrival into an error flag instead of a hang.
-__device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned target, int* err) {
+// this XCD's L2) before the workgroup proceeds.  A bounded spin (spin_limit polls)
+// turns a lost arrival into an error flag instead of a hang: *err is set with a
+// system-scope store (it may live in host memory, where the host reads it at its
+// next call) and the workgroup goes on.
+__device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned target, int* err,
+                                             unsigned spin_limit) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -948,8 +952,8 @@ __device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned target, int
     unsigned spins = 0;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(4);
-      if (++spins > (1u << 25)) {
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (++spins > spin_limit) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         break;
       }
     }
@@ -963,7 +967,8 @@ template <int M, int V, int L>
 __global__ __launch_bounds__((Plan<M, V>::NT)) void k_epoch_persistent(StepArgs a, int n_pos, int B,
                                                                      int ntiles, int nitems,
                                                                      unsigned* bar,
-                                                                     unsigned bar_base, int* err) {
+                                                                     unsigned bar_base, int* err,
+                                                                     unsigned spin_limit) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ float redf[32];
@@ -982,11 +987,11 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_epoch_persistent(StepArgs 
     for (int s = blockIdx.x; s < x.b; s += gridDim.x)
       patch_step<M, V, L>(x, s, A, tws, redf, redd, tid);
     target += gridDim.x;
-    grid_barrier(bar, target, err);
+    grid_barrier(bar, target, err, spin_limit);
     for (int item = blockIdx.x; item < nitems; item += gridDim.x)
       finalize_item<M, NT, FT>(x, item, ntiles, FL, tid);
     target += gridDim.x;
-    grid_barrier(bar, target, err);
+    grid_barrier(bar, target, err, spin_limit);
   }
 }
 
@@ -1277,7 +1282,7 @@ __global__ __launch_bounds__(256 * kGradZGroups) void k_grad_scatter(GradArgs g,
   constexpr int TS = kGradTile, GS = kGradZGroups, U = 8;
   static_assert(TS * TS == 256, "one pixel per thread of a group");
   __shared__ cx<T> part[(GS - 1) * TS * TS];
-  const int tid = threadIdx.x, gi = tid >> 8, q = tid & 255, lane = tid & 63, n = g.n;
+  const int tid = threadIdx.x, gi = tid >> 8, q = tid & 255, lane = tid & 63, n = g.n, nr = g.nr;
   const int tpr = (n + TS - 1) / TS;
   const int ty = (blockIdx.x / tpr) * TS, tx = (blockIdx.x % tpr) * TS;
   const int y = ty + q / TS, x = tx + q % TS;
@@ -1321,7 +1326,7 @@ __global__ __launch_bounds__(256 * kGradZGroups) void k_grad_scatter(GradArgs g,
   }
   if (gi > 0) part[(gi - 1) * TS * TS + q] = acc;
   __syncthreads();
-  if (gi == 0 && y < n && x < n) {
+  if (gi == 0 && y < nr && x < n) {
 #pragma unroll
     for (int k = 1; k < GS; ++k) acc = add(acc, part[(k - 1) * TS * TS + q]);
     const size_t o = (size_t)y * n + x;
@@ -1479,7 +1484,7 @@ hipError_t Launchers<M>::finalize(int f, const StepArgs& a, hipStream_t s, hipEv
   return with_fin(f, [&](auto fc) {
     constexpr int F = decltype(fc)::value, FNT = FinShape<F>::FNT, T = FinShape<F>::T;
     int ntiles;
-    const int items = finalize_items<M, FNT, T>(a.n, a.pgroups, &ntiles);
+    const int items = finalize_items<M, FNT, T>(a.nr, a.n, a.pgroups, &ntiles);
     if (e0) {
       StepArgs aa = a;
       const int4* sl = a.slot;
@@ -1520,11 +1525,11 @@ hipError_t Launchers<M>::finalize_multi(int f, const StepArgs* args, const int2*
 }
 
 template <int M>
-hipError_t Launchers<M>::finalize_item_count(int f, int n, int pgroups, int* items) {
+hipError_t Launchers<M>::finalize_item_count(int f, int nr, int nc, int pgroups, int* items) {
   return with_fin(f, [&](auto fc) {
     constexpr int F = decltype(fc)::value;
     int ntiles = 0;
-    *items = finalize_items<M, FinShape<F>::FNT, FinShape<F>::T>(n, pgroups, &ntiles);
+    *items = finalize_items<M, FinShape<F>::FNT, FinShape<F>::T>(nr, nc, pgroups, &ntiles);
     return hipSuccess;
   });
 }
@@ -1563,21 +1568,22 @@ hipError_t Launchers<M>::persistent_grid_size(int v, int L, int num_cus, int* gr
 template <int M>
 hipError_t Launchers<M>::persistent_epoch(int v, int L, const StepArgs& a, int n_pos, int B,
                                           int grid, unsigned* bar, unsigned bar_base, int* err,
-                                          int* used_grid, hipStream_t s) {
+                                          unsigned spin_limit, int* used_grid, hipStream_t s) {
   return with_plan<M>(v, [&](auto vc) {
     return with_levels(L, [&](auto lc) {
       constexpr int V = decltype(vc)::value, LV = decltype(lc)::value, NT = Plan<M, V>::NT;
       int ntiles;
-      int nitems = finalize_items<M, NT, PersistFin<NT>::T>(a.n, a.pgroups, &ntiles);
+      int nitems = finalize_items<M, NT, PersistFin<NT>::T>(a.nr, a.n, a.pgroups, &ntiles);
       StepArgs aa = a;
       int np = n_pos, bb = B;
       unsigned* br = bar;
       unsigned bb0 = bar_base;
       int* er = err;
+      unsigned sl = spin_limit;
       const int want = max(min(B, n_pos), nitems);
       const int g = max(1, min(grid, want));
       *used_grid = g;
-      void* args[] = {&aa, &np, &bb, &ntiles, &nitems, &br, &bb0, &er};
+      void* args[] = {&aa, &np, &bb, &ntiles, &nitems, &br, &bb0, &er, &sl};
       return hipLaunchCooperativeKernel((const void*)k_epoch_persistent<M, V, LV>, dim3(g),
                                         dim3(NT), args, 0, s);
     });
@@ -1660,12 +1666,12 @@ hipError_t Launchers<M>::chain(int v, int L, const StepArgs& a, int n_steps, hip
 template <typename T, int M, int V>
 static hipError_t grad_t(const GradArgs& g, hipStream_t s) {
   constexpr int NT = Plan<M, V>::NT, TS = kGradTile, PPU = 256 / kGradQGroups;
-  const int tpr = (g.n + TS - 1) / TS;
+  const int tiles = ((g.nr + TS - 1) / TS) * ((g.n + TS - 1) / TS);
   for (int k0 = 0; k0 < g.n_pos; k0 += g.chunk) {
     const int cnt = min(g.chunk, g.n_pos - k0);
     const int first = k0 == 0;
     hipLaunchKernelGGL((k_grad_patch<T, M, V>), dim3(cnt), dim3(NT), 0, s, g, k0);
-    hipLaunchKernelGGL((k_grad_scatter<T, M>), dim3(tpr * tpr), dim3(256 * kGradZGroups), 0, s, g,
+    hipLaunchKernelGGL((k_grad_scatter<T, M>), dim3(tiles), dim3(256 * kGradZGroups), 0, s, g,
                        k0, cnt, first);
     hipLaunchKernelGGL((k_grad_probe<T, M>), dim3((M * M + PPU - 1) / PPU), dim3(256), 0, s, g,
                        cnt, first);

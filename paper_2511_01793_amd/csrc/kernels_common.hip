@@ -100,8 +100,8 @@ hipError_t launch_finalize_multi(int m, int f, const StepArgs* args, const int2*
                                  hipStream_t s) {
   EMG_BY_M(m, finalize_multi(f, args, work, blocks, s));
 }
-hipError_t finalize_item_count(int m, int f, int n, int pgroups, int* items) {
-  EMG_BY_M(m, finalize_item_count(f, n, pgroups, items));
+hipError_t finalize_item_count(int m, int f, int nr, int nc, int pgroups, int* items) {
+  EMG_BY_M(m, finalize_item_count(f, nr, nc, pgroups, items));
 }
 hipError_t launch_plain_step(int m, int v, int L, const StepArgs& a, hipStream_t s) {
   EMG_BY_M(m, plain_step(v, L, a, s));
@@ -111,8 +111,9 @@ hipError_t persistent_grid_size(int m, int v, int L, int num_cus, int* grid) {
 }
 hipError_t launch_persistent_epoch(int m, int v, int L, const StepArgs& a, int n_pos, int minibatch,
                                    int grid, unsigned* bar, unsigned bar_base, int* err,
-                                   int* used_grid, hipStream_t s) {
-  EMG_BY_M(m, persistent_epoch(v, L, a, n_pos, minibatch, grid, bar, bar_base, err, used_grid, s));
+                                   unsigned spin_limit, int* used_grid, hipStream_t s) {
+  EMG_BY_M(m, persistent_epoch(v, L, a, n_pos, minibatch, grid, bar, bar_base, err, spin_limit,
+                               used_grid, s));
 }
 hipError_t launch_layout_intensities(int m, int v, const float* d, float* dperm, int n_pos,
                                      double* pattern_sums, int* bad_flag, hipStream_t s) {

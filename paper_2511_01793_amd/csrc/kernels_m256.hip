@@ -236,7 +236,7 @@ hipError_t Launchers256::finalize(int f, const StepArgs& a, hipStream_t s, hipEv
   return with_fin(f, [&](auto fc) {
     constexpr int F = decltype(fc)::value, FNT = FinShape<F>::FNT, T = FinShape<F>::T;
     int ntiles;
-    const int items = finalize_items<M, FNT, T>(a.n, a.pgroups, &ntiles);
+    const int items = finalize_items<M, FNT, T>(a.nr, a.n, a.pgroups, &ntiles);
     if (e0) {
       StepArgs aa = a;
       const int4* sl = a.slot;
@@ -252,11 +252,11 @@ hipError_t Launchers256::finalize(int f, const StepArgs& a, hipStream_t s, hipEv
   });
 }
 
-hipError_t Launchers256::finalize_item_count(int f, int n, int pgroups, int* items) {
+hipError_t Launchers256::finalize_item_count(int f, int nr, int nc, int pgroups, int* items) {
   return with_fin(f, [&](auto fc) {
     constexpr int F = decltype(fc)::value;
     int ntiles = 0;
-    *items = finalize_items<256, FinShape<F>::FNT, FinShape<F>::T>(n, pgroups, &ntiles);
+    *items = finalize_items<256, FinShape<F>::FNT, FinShape<F>::T>(nr, nc, pgroups, &ntiles);
     return hipSuccess;
   });
 }
@@ -287,7 +287,7 @@ hipError_t Launchers256::finalize_multi(int, const StepArgs*, const int2*, int, 
 }
 hipError_t Launchers256::plain_step(int, int, const StepArgs&, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t Launchers256::persistent_epoch(int, int, const StepArgs&, int, int, int, unsigned*, unsigned,
-                                          int*, int*, hipStream_t) {
+                                          int*, unsigned, int*, hipStream_t) {
   return hipErrorInvalidValue;
 }
 hipError_t Launchers256::misfit(int, const float2*, int, const float2*, const float*, const int2*,

@@ -10,8 +10,9 @@ constexpr int kMaxSlots = 1024;  // patches per minibatch / gradient chunk
 
 struct StepArgs {
   // state (complex64, interleaved)
-  float2* obj;       // n x n
-  int n;
+  float2* obj;       // nr x n (row-major; n is the row stride)
+  int n;             // object columns
+  int nr;            // object rows
   float2* probe;     // m x m
   // measured data in transform order, scan windows
   const float* dperm;  // N x m x m
@@ -58,8 +59,8 @@ hipError_t launch_patch_step_multi(int m, int v, int L, const StepArgs* args, co
                                    int blocks, hipStream_t s);
 hipError_t launch_finalize_multi(int m, int f, const StepArgs* args, const int2* work, int blocks,
                                  hipStream_t s);
-// number of finalize work items (object tiles + probe units) for an n x n object
-hipError_t finalize_item_count(int m, int f, int n, int pgroups, int* items);
+// number of finalize work items (object tiles + probe units) for an nr x nc object
+hipError_t finalize_item_count(int m, int f, int nr, int nc, int pgroups, int* items);
 
 // plain path: the six patch-stage kernels (finalize is launched separately)
 hipError_t launch_plain_step(int m, int v, int L, const StepArgs& a, hipStream_t s);
@@ -67,11 +68,12 @@ hipError_t launch_plain_step(int m, int v, int L, const StepArgs& a, hipStream_t
 // Persistent epoch: one cooperative launch runs every minibatch of a sweep.
 // a.slot must point at the slot list of the whole sweep (N entries); a.b is ignored.
 // `bar` is a device counter that only grows: the kernel's barriers wait for
-// bar_base + (i + 1) * grid arrivals; `err` is set if a barrier wait gives up.
+// bar_base + (i + 1) * grid arrivals; `err` (device-visible, possibly host memory) is set
+// if a barrier wait gives up after spin_limit polls.
 hipError_t persistent_grid_size(int m, int v, int L, int num_cus, int* grid);
 hipError_t launch_persistent_epoch(int m, int v, int L, const StepArgs& a, int n_pos, int minibatch,
                                    int grid, unsigned* bar, unsigned bar_base, int* err,
-                                   int* used_grid, hipStream_t s);
+                                   unsigned spin_limit, int* used_grid, hipStream_t s);
 // zero 64 consecutive unsigned counters
 hipError_t launch_zero_u32(unsigned* p, hipStream_t s);
 
@@ -117,14 +119,15 @@ hipError_t launch_surrogate_terms(int m, int v, const StepArgs& a, double* terms
 // gradient of the misfit (float or double state), chunked over patterns
 struct GradArgs {
   const void* obj;
-  int n;
+  int n;               // object columns (row stride)
+  int nr;              // object rows
   const void* probe;
   const float* dperm;
   const int2* pos;
   int n_pos;
   int chunk;           // patterns per chunk (<= kMaxSlots)
   const void* tw;      // twiddles in the gradient precision
-  void* gobj;          // n x n
+  void* gobj;          // nr x n
   void* gprobe;        // m x m
   void* gz_slots;      // chunk x m^2
   void* gq_slots;      // chunk x m^2
@@ -137,6 +140,12 @@ hipError_t launch_grad(int m, int v, bool f64, const GradArgs& g, hipStream_t s)
 hipError_t launch_misfit_strips(int m, const StepArgs& a, int k0, int count, double* phi_out,
                                 hipStream_t s);
 
+// Calibration kernels (kernels_peak.hip): a copy of n4 16-byte elements with `blocks`
+// workgroups of 256 threads, and a loop of independent FP32 FMAs (iters rounds of 16 per
+// lane; *flops receives the flop count of the launch).
+hipError_t launch_copy16(const void* src, void* dst, size_t n4, int blocks, hipStream_t s);
+hipError_t launch_fma_loop(float* out, int blocks, int iters, hipStream_t s, double* flops);
+
 // The launchers of one probe side (kernels.hpp; instantiated per side in
 // kernels_m32.hip, kernels_m64.hip and kernels_m128.hip).
 template <int M>
@@ -148,12 +157,12 @@ struct Launchers {
                                      int blocks, hipStream_t s);
   static hipError_t finalize_multi(int f, const StepArgs* args, const int2* work, int blocks,
                                    hipStream_t s);
-  static hipError_t finalize_item_count(int f, int n, int pgroups, int* items);
+  static hipError_t finalize_item_count(int f, int nr, int nc, int pgroups, int* items);
   static hipError_t plain_step(int v, int L, const StepArgs& a, hipStream_t s);
   static hipError_t persistent_grid_size(int v, int L, int num_cus, int* grid);
   static hipError_t persistent_epoch(int v, int L, const StepArgs& a, int n_pos, int B, int grid,
-                                     unsigned* bar, unsigned bar_base, int* err, int* used_grid,
-                                     hipStream_t s);
+                                     unsigned* bar, unsigned bar_base, int* err,
+                                     unsigned spin_limit, int* used_grid, hipStream_t s);
   static hipError_t layout(int v, const float* d, float* dperm, int n_pos, double* sums, int* bad,
                            hipStream_t s);
   static hipError_t normalize(float2* probe, double dp_avg, int* flag, hipStream_t s);
@@ -179,12 +188,12 @@ struct Launchers256 {
                                      int blocks, hipStream_t s);
   static hipError_t finalize_multi(int f, const StepArgs* args, const int2* work, int blocks,
                                    hipStream_t s);
-  static hipError_t finalize_item_count(int f, int n, int pgroups, int* items);
+  static hipError_t finalize_item_count(int f, int nr, int nc, int pgroups, int* items);
   static hipError_t plain_step(int v, int L, const StepArgs& a, hipStream_t s);
   static hipError_t persistent_grid_size(int v, int L, int num_cus, int* grid);
   static hipError_t persistent_epoch(int v, int L, const StepArgs& a, int n_pos, int B, int grid,
-                                     unsigned* bar, unsigned bar_base, int* err, int* used_grid,
-                                     hipStream_t s);
+                                     unsigned* bar, unsigned bar_base, int* err,
+                                     unsigned spin_limit, int* used_grid, hipStream_t s);
   static hipError_t layout(int v, const float* d, float* dperm, int n_pos, double* sums, int* bad,
                            hipStream_t s);
   static hipError_t normalize(float2* probe, double dp_avg, int* flag, hipStream_t s);

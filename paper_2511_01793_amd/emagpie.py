@@ -33,7 +33,8 @@ EXPORTS = [
     "emagpie_version", "emagpie_profile_enable", "emagpie_profile_read",
     "emagpie_group_workspace_size", "emagpie_group_create", "emagpie_group_epoch",
     "emagpie_group_destroy", "emagpie_plan_get", "emagpie_plan_describe", "emagpie_check_step",
-    "emagpie_phase_memory_reset",
+    "emagpie_phase_memory_reset", "emagpie_workspace_size_many", "emagpie_init_many",
+    "emagpie_epoch_many", "emagpie_many_member", "emagpie_debug_barrier", "emagpie_measure_peaks",
 ]
 
 
@@ -46,7 +47,8 @@ class EmagpieError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [
-        ("n", ctypes.c_int32), ("m", ctypes.c_int32), ("n_pos", ctypes.c_int32),
+        ("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32), ("m", ctypes.c_int32),
+        ("n_pos", ctypes.c_int32),
         ("minibatch", ctypes.c_int32), ("levels", ctypes.c_int32),
         ("alpha", ctypes.c_float), ("alpha_z", ctypes.c_float),
         ("update_probe", ctypes.c_int32), ("joint_step", ctypes.c_int32), ("path", ctypes.c_int32),
@@ -112,22 +114,35 @@ def lib() -> ctypes.CDLL:
         "emagpie_check_step": [vp, vp, vp, vp, i32, vp, vp],
         "emagpie_phase_memory_reset": [vp, vp],
         "emagpie_plan_describe": [i32, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(i32)],
+        "emagpie_workspace_size_many": [i32, vp, ctypes.POINTER(sz)],
+        "emagpie_init_many": [ctypes.POINTER(vp), i32, vp, vp, vp, vp, sz, vp],
+        "emagpie_epoch_many": [vp, vp, vp, i64, vp, vp],
+        "emagpie_many_member": [vp, i32, ctypes.POINTER(vp)],
+        "emagpie_debug_barrier": [vp, ctypes.c_uint32, ctypes.c_uint32],
+        "emagpie_measure_peaks": [vp, sz, i32, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int
     L.emagpie_last_error.restype = ctypes.c_char_p
-    L.emagpie_last_error.argtypes = []
+    L.emagpie_last_error.argtypes = [vp]
     L.emagpie_version.restype = ctypes.c_char_p
     L.emagpie_version.argtypes = []
     _lib = L
     return L
 
 
-def _check(st: int):
+def _check(st: int, ctx=None):
+    """Raise on a failed call; the message is ctx's last failure (or the thread's)."""
     if st != 0:
-        raise EmagpieError(st, lib().emagpie_last_error().decode())
+        raise EmagpieError(st, last_error(ctx))
+
+
+def last_error(ctx=None) -> str:
+    """Message of the last failure of a call on ctx (a ctypes handle), or on this thread."""
+    h = None if ctx is None else (ctx.value if isinstance(ctx, ctypes.c_void_p) else ctx)
+    return lib().emagpie_last_error(h).decode()
 
 
 def _stream() -> int:
@@ -171,11 +186,11 @@ class Reconstruction:
     """One reconstruction problem bound to a libemagpie context.
 
     positions: (N, 2) int (row, col) top-left corners; intensities: (N, m, m) float32 CUDA
-    tensor (unshifted).  The object (n x n) and probe (m x m) are complex64 CUDA tensors
-    owned by the caller and updated in place.
+    tensor (unshifted); n: the object side, or its (rows, cols).  The object (rows x cols)
+    and probe (m x m) are complex64 CUDA tensors owned by the caller and updated in place.
     """
 
-    def __init__(self, positions, intensities: torch.Tensor, n: int, *, minibatch: int,
+    def __init__(self, positions, intensities: torch.Tensor, n, *, minibatch: int,
                  levels: int = 1, alpha: float = 0.05, alpha_z: float = 1.0,
                  update_probe: bool = True, joint_step: bool = True, path: str = "graph",
                  seed: int = 0, fft_plan: int = 0, finalize_shape: int = 0,
@@ -187,8 +202,11 @@ class Reconstruction:
         N, m, m2 = intensities.shape
         if m != m2 or N != pos.shape[0]:
             raise ValueError("intensities must be (N, m, m) with N = len(positions)")
-        self.n, self.m, self.n_pos = int(n), int(m), int(N)
-        self.cfg = Config(n=self.n, m=self.m, n_pos=self.n_pos, minibatch=int(minibatch),
+        rows, cols = (int(n), int(n)) if np.ndim(n) == 0 else (int(n[0]), int(n[1]))
+        self.shape = (rows, cols)
+        self.n = rows if rows == cols else self.shape
+        self.m, self.n_pos = int(m), int(N)
+        self.cfg = Config(n_rows=rows, n_cols=cols, m=self.m, n_pos=self.n_pos, minibatch=int(minibatch),
                           levels=int(levels), alpha=float(alpha), alpha_z=float(alpha_z),
                           update_probe=int(bool(update_probe)), joint_step=int(bool(joint_step)),
                           path=PATHS[path],
@@ -220,36 +238,36 @@ class Reconstruction:
 
     # -- timing -----------------------------------------------------------
     def profile(self, enable: bool = True):
-        _check(lib().emagpie_profile_enable(self._ctx, int(bool(enable))))
+        _check(lib().emagpie_profile_enable(self._ctx, int(bool(enable))), self._ctx)
 
     def profile_read(self):
         """{'patch': (ms, launches), 'finalize': (...), 'persistent': (...)} since the last read."""
         ms = np.zeros(3, dtype=np.float64)
         cnt = np.zeros(3, dtype=np.int64)
-        _check(lib().emagpie_profile_read(self._ctx, ms.ctypes.data, cnt.ctypes.data))
+        _check(lib().emagpie_profile_read(self._ctx, ms.ctypes.data, cnt.ctypes.data), self._ctx)
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(["patch", "finalize", "persistent"])}
 
     # -- operations -------------------------------------------------------
     @property
     def dp_avg(self) -> float:
         out = ctypes.c_double(0)
-        _check(lib().emagpie_dp_avg(self._ctx, ctypes.byref(out)))
+        _check(lib().emagpie_dp_avg(self._ctx, ctypes.byref(out)), self._ctx)
         return out.value
 
     @property
     def plan(self) -> dict:
         """The kernel plan this context runs with (after any autotuning at init)."""
         p = Plan()
-        _check(lib().emagpie_plan_get(self._ctx, ctypes.byref(p)))
+        _check(lib().emagpie_plan_get(self._ctx, ctypes.byref(p)), self._ctx)
         return p.as_dict()
 
     def _state(self, obj, probe, dtype=torch.complex64):
-        _expect(obj, dtype, (self.n, self.n), "object")
+        _expect(obj, dtype, self.shape, "object")
         _expect(probe, dtype, (self.m, self.m), "probe")
 
     def normalize_probe(self, probe: torch.Tensor):
         _expect(probe, torch.complex64, (self.m, self.m), "probe")
-        _check(lib().emagpie_normalize_probe(self._ctx, probe.data_ptr(), _stream()))
+        _check(lib().emagpie_normalize_probe(self._ctx, probe.data_ptr(), _stream()), self._ctx)
 
     def _indices(self, idx) -> torch.Tensor:
         t = torch.as_tensor(idx, dtype=torch.int32)
@@ -264,7 +282,7 @@ class Reconstruction:
         self._state(obj, probe)
         d_idx = self._indices(idx)
         _check(lib().emagpie_step_minibatch(self._ctx, obj.data_ptr(), probe.data_ptr(),
-                                            d_idx.data_ptr(), d_idx.numel(), _ptr(sampled), _stream()))
+                                            d_idx.data_ptr(), d_idx.numel(), _ptr(sampled), _stream()), self._ctx)
         return d_idx
 
     def epoch(self, obj, probe, epoch: int, perm: torch.Tensor | None = None,
@@ -273,11 +291,22 @@ class Reconstruction:
         if perm is not None:
             _expect(perm, torch.int32, (self.n_pos,), "perm")
         _check(lib().emagpie_epoch(self._ctx, obj.data_ptr(), probe.data_ptr(), int(epoch),
-                                   _ptr(perm), _ptr(sampled), _stream()))
+                                   _ptr(perm), _ptr(sampled), _stream()), self._ctx)
 
     def reset_phase_memory(self):
         """Zero-bin phase memory back to the first-sweep state (theta = 0 everywhere)."""
-        _check(lib().emagpie_phase_memory_reset(self._ctx, _stream()))
+        _check(lib().emagpie_phase_memory_reset(self._ctx, _stream()), self._ctx)
+
+    def debug_barrier(self, spin_limit: int = 0, target_skew: int = 0):
+        """Fault injection for the persistent path's error reporting (tests only): grid
+        barriers of later persistent epochs poll at most spin_limit times (0: default) and
+        wait for target_skew extra arrivals, so with target_skew > 0 every wait gives up and
+        the next call raises E_HIP."""
+        _check(lib().emagpie_debug_barrier(self._ctx, int(spin_limit), int(target_skew)), self._ctx)
+
+    @property
+    def last_error(self) -> str:
+        return last_error(self._ctx)
 
     def check_step(self, obj, probe, idx) -> torch.Tensor:
         """One minibatch update (as step()) that also returns, in float64 on the device,
@@ -286,7 +315,7 @@ class Reconstruction:
         t = self._indices(idx)
         out = torch.empty(3, dtype=torch.float64, device="cuda")
         _check(lib().emagpie_check_step(self._ctx, obj.data_ptr(), probe.data_ptr(), t.data_ptr(),
-                                        t.numel(), out.data_ptr(), _stream()))
+                                        t.numel(), out.data_ptr(), _stream()), self._ctx)
         return out
 
     def mg_cycle(self, obj, probe, idx) -> torch.Tensor:
@@ -294,7 +323,7 @@ class Reconstruction:
         d_idx = self._indices(idx)
         out = torch.empty((d_idx.numel(), self.m, self.m), dtype=torch.complex64, device="cuda")
         _check(lib().emagpie_mg_cycle(self._ctx, obj.data_ptr(), probe.data_ptr(), d_idx.data_ptr(),
-                                      d_idx.numel(), out.data_ptr(), _stream()))
+                                      d_idx.numel(), out.data_ptr(), _stream()), self._ctx)
         return out
 
     def misfit(self, obj, probe, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -302,7 +331,7 @@ class Reconstruction:
         if out is None:
             out = torch.empty((), dtype=torch.float64, device="cuda")
         _check(lib().emagpie_misfit(self._ctx, obj.data_ptr(), probe.data_ptr(), out.data_ptr(),
-                                    _stream()))
+                                    _stream()), self._ctx)
         return out
 
     def grad(self, obj, probe):
@@ -313,7 +342,7 @@ class Reconstruction:
         gprobe = torch.empty_like(probe)
         phi = torch.empty((), dtype=torch.float64, device="cuda")
         _check(lib().emagpie_grad(self._ctx, obj.data_ptr(), probe.data_ptr(), gobj.data_ptr(),
-                                  gprobe.data_ptr(), phi.data_ptr(), F64 if f64 else F32, _stream()))
+                                  gprobe.data_ptr(), phi.data_ptr(), F64 if f64 else F32, _stream()), self._ctx)
         return gobj, gprobe, phi
 
 
@@ -381,3 +410,104 @@ class Group:
             self.close()
         except Exception:
             pass
+
+
+class Many:
+    """Several independent reconstructions behind one library context
+    (emagpie_init_many / emagpie_epoch_many); member i is a Reconstruction-like view for the
+    per-instance calls.  Bitwise the same as a Group of separately made Reconstructions.
+
+    problems: a list of dicts with the Reconstruction arguments (positions, intensities, n,
+    minibatch, levels, alpha, alpha_z, update_probe, joint_step, path, seed, fft_plan,
+    finalize_shape, zero_phase_memory).
+    """
+
+    def __init__(self, problems):
+        n = len(problems)
+        cfgs = (Config * n)()
+        self._pos, self._inten, self.members = [], [], []
+        for i, pr in enumerate(problems):
+            pos = np.ascontiguousarray(np.asarray(pr["positions"], dtype=np.int32).reshape(-1, 2))
+            d = pr["intensities"].contiguous()
+            N, m, _ = d.shape
+            nn = pr["n"]
+            rows, cols = (int(nn), int(nn)) if np.ndim(nn) == 0 else (int(nn[0]), int(nn[1]))
+            cfgs[i] = Config(n_rows=rows, n_cols=cols, m=int(m), n_pos=int(N),
+                             minibatch=int(pr["minibatch"]), levels=int(pr.get("levels", 1)),
+                             alpha=float(pr.get("alpha", 0.05)), alpha_z=float(pr.get("alpha_z", 1.0)),
+                             update_probe=int(bool(pr.get("update_probe", True))),
+                             joint_step=int(bool(pr.get("joint_step", True))),
+                             path=PATHS[pr.get("path", "graph")],
+                             seed=int(pr.get("seed", 0)) & ((1 << 64) - 1),
+                             fft_plan=int(pr.get("fft_plan", 0)),
+                             finalize_shape=int(pr.get("finalize_shape", 0)), tune_cache=None,
+                             zero_phase_memory=int(bool(pr.get("zero_phase_memory", False))))
+            self._pos.append(pos)
+            self._inten.append(d)
+        self._cfgs = cfgs
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().emagpie_workspace_size_many(n, cfgs, ctypes.byref(nbytes)))
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self._ws.data_ptr() + 255) & ~255
+        pos_arr = (ctypes.c_void_p * n)(*[p.ctypes.data for p in self._pos])
+        int_arr = (ctypes.c_void_p * n)(*[d.data_ptr() for d in self._inten])
+        self._ctx = ctypes.c_void_p(None)
+        _check(lib().emagpie_init_many(ctypes.byref(self._ctx), n, cfgs, pos_arr, int_arr, ptr,
+                                       nbytes.value, _stream()))
+        self._inten = None  # copied into the workspace at init
+        for i in range(n):
+            h = ctypes.c_void_p(None)
+            _check(lib().emagpie_many_member(self._ctx, i, ctypes.byref(h)), self._ctx)
+            self.members.append(_Member(h, cfgs[i], self._pos[i]))
+
+    def epoch(self, objs, probes, epoch: int, sampled: torch.Tensor | None = None):
+        n = len(self.members)
+        if len(objs) != n or len(probes) != n:
+            raise ValueError("one object and one probe per member")
+        for r, o, q in zip(self.members, objs, probes):
+            r._state(o, q)
+        if sampled is not None:
+            _expect(sampled, torch.float64, (n,), "sampled")
+        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in objs])
+        pp = (ctypes.c_void_p * n)(*[q.data_ptr() for q in probes])
+        _check(lib().emagpie_epoch_many(self._ctx, op, pp, int(epoch), _ptr(sampled), _stream()),
+               self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            torch.cuda.current_stream().synchronize()
+            for r in self.members:
+                r._ctx = ctypes.c_void_p(None)  # owned by the many-context
+            lib().emagpie_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Member(Reconstruction):
+    """A member context of a Many (borrowed handle: closing it does nothing)."""
+
+    def __init__(self, handle, cfg, positions):  # noqa: D401 - no Reconstruction.__init__
+        self._ctx = handle
+        self.cfg = cfg
+        self.shape = (int(cfg.n_rows), int(cfg.n_cols))
+        self.n = self.shape[0] if self.shape[0] == self.shape[1] else self.shape
+        self.m, self.n_pos = int(cfg.m), int(cfg.n_pos)
+        self.positions = positions
+
+    def close(self):
+        pass
+
+
+def measure_peaks(nbytes: int = 1 << 30, reps: int = 5) -> dict:
+    """Measured copy bandwidth (GB/s) and FP32 FMA rate (TFLOP/s) of the current device."""
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = (buf.data_ptr() + 255) & ~255
+    out = np.zeros(2, dtype=np.float64)
+    _check(lib().emagpie_measure_peaks(ptr, nbytes, int(reps), out.ctypes.data, _stream()))
+    return {"copy_GBs": float(out[0]), "fp32_fma_TFLOPs": float(out[1]), "copy_bytes": nbytes,
+            "reps": reps}

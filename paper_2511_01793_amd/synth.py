@@ -36,6 +36,7 @@ __all__ = [
     "make_object",
     "true_probe",
     "initial_probe",
+    "jittered_initial_probe",
     "raster_positions",
     "fermat_positions",
     "simulate_intensities",
@@ -89,6 +90,19 @@ def initial_probe(m: int, sigma: float | None = None) -> np.ndarray:
     c = (m - 1) / 2.0
     yy, xx = np.mgrid[0:m, 0:m].astype(np.float64)
     return np.exp(-((yy - c) ** 2 + (xx - c) ** 2) / (2.0 * s * s)).astype(np.complex128)
+
+
+def jittered_initial_probe(probe_init: np.ndarray, eps: float, seed: int) -> np.ndarray:
+    """The initial probe times (1 + eps g), g complex standard normal per pixel drawn from
+    default_rng(seed) (real and imaginary parts each N(0, 1/2)); complex64 like probe_init.
+    eps = 0 returns probe_init unchanged.  Seeded variants of one start, for the spread of
+    the time to a fixed misfit."""
+    if eps == 0.0:
+        return probe_init.copy()
+    rng = np.random.default_rng(seed)
+    shape = probe_init.shape
+    g = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2.0)
+    return (probe_init.astype(np.complex128) * (1.0 + eps * g)).astype(probe_init.dtype)
 
 
 def raster_positions(n: int, m: int, side: int, step: int, jitter: int,

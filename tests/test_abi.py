@@ -34,6 +34,9 @@ def cfg(**kw):
     base = dict(n=128, m=32, n_pos=100, minibatch=10, levels=1, alpha=0.01, alpha_z=1.0,
                 update_probe=1, joint_step=1, path=0, seed=0)
     base.update(kw)
+    n = base.pop("n")
+    base.setdefault("n_rows", n)
+    base.setdefault("n_cols", n)
     return E.Config(**base)
 
 
@@ -63,7 +66,7 @@ def _init(c, positions, ws_ptr, ws_bytes):
     pos = np.ascontiguousarray(np.asarray(positions, dtype=np.int32))
     st = E.lib().emagpie_init(ctypes.byref(ctx), ctypes.byref(c), pos.ctypes.data, 0x1000,
                               ws_ptr, ws_bytes, None)
-    return st, E.lib().emagpie_last_error().decode()
+    return st, E.last_error()
 
 
 def test_init_rejects_positions_outside_object():
@@ -156,3 +159,55 @@ def test_probe_side_256_configuration():
     with pytest.raises(E.EmagpieError) as ei:
         E.workspace_size(cfg(m=256, n=200, path=1))
     assert ei.value.name == "E_SHAPE"
+
+
+def test_rectangular_objects_validated_per_side():
+    # rows and columns are checked on their own: 100 x 300 takes windows up to (68, 268)
+    c = cfg(n_rows=100, n_cols=300, n_pos=3)
+    ws = E.workspace_size(c)
+    assert ws > 0
+    st, msg = _init(c, [[0, 0], [10, 10], [0, 269]], 0x100000, ws)
+    assert E.STATUS[st] == "E_POSITION" and "scan position 2" in msg
+    st, msg = _init(c, [[0, 0], [10, 10], [69, 0]], 0x100000, ws)
+    assert E.STATUS[st] == "E_POSITION"
+    for bad in (dict(n_rows=16, n_cols=300), dict(n_rows=300, n_cols=31), dict(n_cols=70000)):
+        with pytest.raises(E.EmagpieError) as ei:
+            E.workspace_size(cfg(**bad))
+        assert ei.value.name == "E_SHAPE"
+
+
+def test_last_error_per_context_and_per_thread():
+    # with no context the thread's last failure; a null context is an argument error
+    with pytest.raises(E.EmagpieError):
+        E.workspace_size(cfg(m=48))
+    assert "probe side" in E.last_error()
+    st = E.lib().emagpie_epoch(None, 0x1000, 0x1000, 0, None, None, None)
+    assert E.STATUS[st] == "E_ARG" and "null context" in E.last_error()
+
+
+def test_many_instance_configuration():
+    one = E.workspace_size(cfg())
+    two = (E.Config * 2)(cfg(), cfg(n=256, m=64, n_pos=400, minibatch=64, levels=2))
+    out = ctypes.c_size_t(0)
+    assert E.lib().emagpie_workspace_size_many(2, two, ctypes.byref(out)) == 0
+    assert out.value > one + E.workspace_size(cfg(n=256, m=64, n_pos=400, minibatch=64, levels=2))
+    # sizing with a finalize shape left to the autotuner is an upper bound over the shapes
+    tuned = (E.Config * 2)(cfg(), cfg(n=256, m=64, n_pos=400, minibatch=64, levels=2,
+                                      finalize_shape=E.TUNE))
+    out2 = ctypes.c_size_t(0)
+    assert E.lib().emagpie_workspace_size_many(2, tuned, ctypes.byref(out2)) == 0
+    assert out2.value >= out.value
+    bad = (E.Config * 2)(cfg(), cfg(m=256, n=300, path=1))
+    assert E.STATUS[E.lib().emagpie_workspace_size_many(2, bad, ctypes.byref(out))] == "E_UNSUPPORTED"
+    assert E.STATUS[E.lib().emagpie_workspace_size_many(0, two, ctypes.byref(out))] == "E_ARG"
+    ctx = ctypes.c_void_p(None)
+    st = E.lib().emagpie_init_many(ctypes.byref(ctx), 2, two, None, None, 0x100000, 1 << 40, None)
+    assert E.STATUS[st] == "E_ARG" and not ctx.value
+
+
+def test_peak_measurement_rejects_small_buffers():
+    out = np.zeros(2)
+    st = E.lib().emagpie_measure_peaks(0x100000, 1 << 20, 3, out.ctypes.data, None)
+    assert E.STATUS[st] == "E_WORKSPACE"
+    st = E.lib().emagpie_measure_peaks(0x100000, 1 << 30, 0, out.ctypes.data, None)
+    assert E.STATUS[st] == "E_ARG"

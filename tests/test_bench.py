@@ -32,8 +32,37 @@ def test_algorithmic_bytes_by_hand():
 
 
 def test_recorded_traffic_follows_the_sources(monkeypatch):
-    t = bench.recorded_traffic("c2", 0)
+    import json
+    rec = None
+    with open(os.path.join(ROOT, "profiles", "patch_step_traffic.md")) as f:
+        for line in f:
+            if line.startswith("traffic_json: "):
+                rec = json.loads(line[len("traffic_json: "):])
+    assert rec is not None
+    key = next(k for k in rec if "/plan" in k)
+    wl, plan = key.split("/plan")
+    # reported while the kernel sources match the digest recorded with the counters ...
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: rec["source"])
+    t = bench.recorded_traffic(wl, int(plan))
     assert t is not None and t > 0
-    assert bench.recorded_traffic("c2", 7) is None  # no such plan recorded
+    assert bench.recorded_traffic(wl, 7) is None  # no such plan recorded
+    # ... and null once they differ
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0000000000000000")
-    assert bench.recorded_traffic("c2", 0) is None
+    assert bench.recorded_traffic(wl, int(plan)) is None
+
+
+def test_time_to_target_spread_and_targets():
+    assert bench.spread([None, None]) is None
+    s = bench.spread([3.0, None, 1.0, 2.0])
+    assert s == {"median": 2.0, "min": 1.0, "max": 3.0, "runs": 3}
+    t = bench.load_targets("c2")
+    assert "c2" in t and all(k == "c2" or k.startswith("c2/") for k in t)
+    for v in t.values():
+        assert abs(v["target"] - 1.01 * v["final"]) <= 1e-9 * v["target"]
+        assert v["misfit"][-1] == v["final"] and len(v["misfit"]) == v["epochs"] + 1
+
+
+def test_algorithmic_flops_per_pattern():
+    # 64^2: two 2-D FFTs of 5 N log2 N flops (N = 4096, log2 N = 12) and 80 flops per pixel
+    assert bench.algorithmic_flops_pattern(64) == 2 * 5 * 4096 * 12 + 80 * 4096
+    assert abs(bench.VALU_PEAK_TFLOPS - 78.6432) < 1e-3
