@@ -345,6 +345,30 @@ emagpie_status emagpie_epoch_many(emagpie_ctx ctx, void* const* obj_devs, void* 
 emagpie_status emagpie_many_member(emagpie_ctx ctx, int32_t i, emagpie_ctx* member_out);
 
 /*
+ * Exit-wave misfit Phi(Q, z) of Eq. 1, like emagpie_misfit, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): it needs no context and no workspace, and calls no allocating
+ * routine.  Its scratch, the per-pattern terms, is a fixed array of the library's own
+ * (at most 65536 patterns: 512 KiB per device, held until the process ends).  Every call
+ * on a device shares that device's array, so calls that overlap on one device (several
+ * streams) race; calls ordered on one stream do not.
+ *   positions_dev: n_pos x 2 int32 (row, col) window corners on the device; they must
+ *     satisfy 0 <= row <= n_rows - m, 0 <= col <= n_cols - m (not checked on the host:
+ *     the kernel clamps each window into the object, so no access leaves the buffers, and
+ *     the value for an invalid window is undefined);
+ *   intensities_dev: n_pos x m x m float32 measured intensities, natural (unshifted)
+ *     order, read in place;
+ *   obj_dev (n_rows x n_cols), probe_dev (m x m): complex64; misfit_dev: one double.
+ * m = 32, 64 or 128 (EMAGPIE_E_UNSUPPORTED for 256); 1 <= n_pos <= 65536 (EMAGPIE_E_SHAPE
+ * otherwise).  The arithmetic is that of emagpie_misfit with FFT plan 0, so the value is
+ * bitwise the one a context with plan 0 returns for the same inputs.  Stream-ordered.
+ */
+emagpie_status emagpie_misfit_noalloc(int32_t n_rows, int32_t n_cols, int32_t m, int32_t n_pos,
+                                      const int32_t* positions_dev, const float* intensities_dev,
+                                      const void* obj_dev, const void* probe_dev, double* misfit_dev,
+                                      void* stream);
+
+/*
  * Fault-injection hook for the device-side error path of the persistent epoch
  * (tests only).  Later persistent epochs of ctx poll each grid barrier at most
  * spin_limit times (0 restores the default, 2^25) and wait for target_skew more

@@ -26,6 +26,15 @@ emagpie_status fail(emagpie_status st, const std::string& msg) {
   return st;
 }
 
+}  // namespace
+
+namespace emg {
+// failure message of a call made outside this file (the no-allocation misfit)
+emagpie_status set_error(emagpie_status st, const std::string& msg) { return fail(st, msg); }
+}  // namespace emg
+
+namespace {
+
 #define EMG_HIP(expr)                                                                    \
   do {                                                                                   \
     hipError_t e_ = (expr);                                                              \

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libemagpie.so")
-SOURCES = ["kernels_m32.hip", "kernels_m64.hip", "kernels_m128.hip", "kernels_m256.hip", "kernels_peak.hip",
+SOURCES = ["kernels_m32.hip", "kernels_m64.hip", "kernels_m128.hip", "kernels_m256.hip", "kernels_peak.hip", "noalloc.hip",
            "kernels_common.hip", "api.hip"]
 
 # Packed FP32 VALU forms are disabled on purpose: every FP32 operation is a

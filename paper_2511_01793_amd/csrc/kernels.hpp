@@ -1118,21 +1118,16 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_numerators(StepArgs a) {
 // ---------------------------------------------------------------------------
 // misfit and gradient
 // ---------------------------------------------------------------------------
-template <int M, int V>
-__global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, int n,
-                                                        const float2* probe, const float* dperm,
-                                                        const int2* pos, const int4* slot,
-                                                        const float2* tw, double* phi_all) {
-  __shared__ cx<float> A[M * lds_stride<M>()];
-  __shared__ cx<float> tws[M];
-  __shared__ double redd[16];
+// Misfit term Phi_k = sum (|F(Q . z_k)| - a_k)^2 / (2 m^2) of one pattern (Eq. 1, Parseval
+// form), returned in thread 0.  The twiddles are already in tws (the caller synchronises
+// after staging them).  INT(row, col) is the measured intensity at transform-order position
+// (row, col): dk[row * M + col] for intensities laid out in the plan's transform order, or
+// d[freq(row) * M + freq(col)] for intensities in natural order.
+template <int M, int V, class INT>
+__device__ __forceinline__ double misfit_pattern(const float2* obj, int n, const float2* probe,
+                                                 int2 pk, INT intensity, cx<float>* A,
+                                                 const cx<float>* tws, double* redd, int tid) {
   constexpr int PX = Px<M, V>::PX, NT = Px<M, V>::NT, LS = Px<M, V>::LS;
-  // all patterns (slot == nullptr: block k is pattern k) or the patterns of a slot list
-  const int tid = threadIdx.x;
-  const int k = slot ? slot[blockIdx.x].x : (int)blockIdx.x;
-  const int2 pk = slot ? make_int2(slot[blockIdx.x].y, slot[blockIdx.x].z) : pos[k];
-  const float* dk = dperm + (size_t)k * M * M;
-  stage_twiddles<M, NT>(tw, tws, tid);
 #pragma unroll
   for (int e = 0; e < PX; ++e) {
     int r, c;
@@ -1148,7 +1143,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, 
     if (CP::ITEMS < CP::NT && w >= CP::ITEMS) break;
     const int line = w % M, g = w / M;
 #pragma unroll
-    for (int j = 0; j < CP::R1; ++j) dv[it * CP::R1 + j] = dk[(CP::R1 * g + j) * M + line];
+    for (int j = 0; j < CP::R1; ++j) dv[it * CP::R1 + j] = intensity(CP::R1 * g + j, line);
   }
   __syncthreads();
   fft_pass<float, M, V, false, true, false>(A, tws, tid);
@@ -1163,7 +1158,28 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, 
     acc += (double)project_px<M>(P, dv[e]);
   });
   const double tot = block_sum<NT>(acc, redd, tid);
-  if (tid == 0) phi_all[blockIdx.x] = tot / (2.0 * M * M);
+  return tot / (2.0 * M * M);
+}
+
+template <int M, int V>
+__global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, int n,
+                                                        const float2* probe, const float* dperm,
+                                                        const int2* pos, const int4* slot,
+                                                        const float2* tw, double* phi_all) {
+  __shared__ cx<float> A[M * lds_stride<M>()];
+  __shared__ cx<float> tws[M];
+  __shared__ double redd[16];
+  constexpr int NT = Px<M, V>::NT;
+  // all patterns (slot == nullptr: block k is pattern k) or the patterns of a slot list
+  const int tid = threadIdx.x;
+  const int k = slot ? slot[blockIdx.x].x : (int)blockIdx.x;
+  const int2 pk = slot ? make_int2(slot[blockIdx.x].y, slot[blockIdx.x].z) : pos[k];
+  const float* dk = dperm + (size_t)k * M * M;
+  stage_twiddles<M, NT>(tw, tws, tid);
+  const double phi = misfit_pattern<M, V>(obj, n, probe, pk,
+                                          [&](int r, int c) { return dk[r * M + c]; }, A, tws,
+                                          redd, tid);
+  if (tid == 0) phi_all[blockIdx.x] = phi;
 }
 
 // Quadratic surrogate of Eq. 3 for the slots of a batch: 1/2 ||Q . z_k - R_k||^2 with the

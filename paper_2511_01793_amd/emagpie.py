@@ -35,6 +35,7 @@ EXPORTS = [
     "emagpie_group_destroy", "emagpie_plan_get", "emagpie_plan_describe", "emagpie_check_step",
     "emagpie_phase_memory_reset", "emagpie_workspace_size_many", "emagpie_init_many",
     "emagpie_epoch_many", "emagpie_many_member", "emagpie_debug_barrier", "emagpie_measure_peaks",
+    "emagpie_misfit_noalloc",
 ]
 
 
@@ -120,6 +121,7 @@ def lib() -> ctypes.CDLL:
         "emagpie_many_member": [vp, i32, ctypes.POINTER(vp)],
         "emagpie_debug_barrier": [vp, ctypes.c_uint32, ctypes.c_uint32],
         "emagpie_measure_peaks": [vp, sz, i32, vp, vp],
+        "emagpie_misfit_noalloc": [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -511,3 +513,22 @@ def measure_peaks(nbytes: int = 1 << 30, reps: int = 5) -> dict:
     _check(lib().emagpie_measure_peaks(ptr, nbytes, int(reps), out.ctypes.data, _stream()))
     return {"copy_GBs": float(out[0]), "fp32_fma_TFLOPs": float(out[1]), "copy_bytes": nbytes,
             "reps": reps}
+
+
+def misfit_noalloc(positions: torch.Tensor, intensities: torch.Tensor, obj: torch.Tensor,
+                   probe: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Phi of Eq. 1 through emagpie_misfit_noalloc (no context, no workspace): positions
+    (N, 2) int32 and intensities (N, m, m) float32 (natural order), object and probe
+    complex64, all CUDA tensors."""
+    N = positions.shape[0]
+    m = probe.shape[0]
+    _expect(positions, torch.int32, (N, 2), "positions")
+    _expect(intensities, torch.float32, (N, m, m), "intensities")
+    _expect(probe, torch.complex64, (m, m), "probe")
+    _expect(obj, torch.complex64, tuple(obj.shape), "object")
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device="cuda")
+    _check(lib().emagpie_misfit_noalloc(obj.shape[0], obj.shape[1], m, N, positions.data_ptr(),
+                                        intensities.data_ptr(), obj.data_ptr(), probe.data_ptr(),
+                                        out.data_ptr(), _stream()))
+    return out
