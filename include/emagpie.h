@@ -93,7 +93,8 @@ typedef struct {
   uint64_t seed;        /* scan-order generator seed                                */
   int32_t fft_plan;     /* kernel shape of the patch stage: 0 .. count-1 (see
                            emagpie_plan_describe; 0 is the default), or EMAGPIE_TUNE */
-  int32_t finalize_shape; /* finalize work-item shape 0..3 (0 default), or EMAGPIE_TUNE */
+  int32_t finalize_shape; /* finalize shape 0..11 (0 default; see emagpie_plan_describe),
+                           or EMAGPIE_TUNE                                              */
   const char* tune_cache; /* NULL, or a file of autotuning results (JSON lines) that
                            emagpie_init reads before timing and appends to after  */
   int32_t zero_phase_memory; /* 1: the stateful zero-bin phase rule stated after Eq. 3
@@ -106,20 +107,20 @@ typedef struct {
  * Kernel plan of a context.  The FFT plan fixes the radix split m = r1 * r2 of
  * the LDS transforms and the threads per patch; the finalize shape fixes the
  * threads per work item, the object tile side and the order the workgroups take
- * the tiles in (fin_banded 0: row-major; 1: contiguous bands of tile rows per
- * XCD).  Plans that share (r1, r2) give bitwise-identical results; other splits
+ * the tiles in (fin_order 0: row-major; 1: contiguous bands of tile rows per
+ * XCD; 2: tile rows dealt to the XCDs in turn, row r to XCD r mod 8).  Plans that share (r1, r2) give bitwise-identical results; other splits
  * round the same transform differently (and lay the intensities out in their
  * own order).  Finalize shapes never change results.
  */
 typedef struct {
   int32_t fft_plan, r1, r2, threads;
-  int32_t finalize_shape, fin_threads, fin_tile, fin_banded;
+  int32_t finalize_shape, fin_threads, fin_tile, fin_order;
   int32_t path;          /* EMAGPIE_PATH_* in use (never AUTO)                       */
   int32_t tuned;         /* 0 fixed by the config, 1 timed at init, 2 from tune_cache */
   int32_t n_fft_plans;   /* candidates timed (0 if the FFT plan was not timed)      */
   float fft_us[4];       /* median patch-stage kernel time per candidate, us        */
   int32_t n_fin_shapes;  /* candidates timed (0 if the shape was not timed)         */
-  float fin_us[8];       /* median finalize kernel time per candidate, us           */
+  float fin_us[12];      /* median finalize kernel time per candidate, us           */
   float path_ms[8];      /* median epoch time per path (index EMAGPIE_PATH_*), ms; -1
                             where not timed (PLAIN is never a candidate)            */
 } emagpie_plan;

@@ -180,7 +180,8 @@ emagpie_status check_config(const emagpie_config* c) {
     return fail(EMAGPIE_E_ARG, "fft_plan must be EMAGPIE_TUNE or in [0, " +
                                    std::to_string(emg::fft_plan_count(c->m)) + ") for this m");
   if (c->finalize_shape != EMAGPIE_TUNE && (c->finalize_shape < 0 || c->finalize_shape >= emg::kFinShapes))
-    return fail(EMAGPIE_E_ARG, "finalize_shape must be EMAGPIE_TUNE or in [0, 4)");
+    return fail(EMAGPIE_E_ARG, "finalize_shape must be EMAGPIE_TUNE or in [0, " +
+                                   std::to_string(emg::kFinShapes) + ")");
   return EMAGPIE_OK;
 }
 
@@ -380,7 +381,7 @@ void fill_plan_info(emagpie_ctx c, int tuned) {
   p.fft_plan = c->cfg.fft_plan;
   emg::fft_plan_desc(c->cfg.m, p.fft_plan, &p.r1, &p.r2, &p.threads);
   p.finalize_shape = c->cfg.finalize_shape;
-  emg::fin_shape_desc(p.finalize_shape, &p.fin_threads, &p.fin_tile, &p.fin_banded);
+  emg::fin_shape_desc(p.finalize_shape, &p.fin_threads, &p.fin_tile, &p.fin_order);
   p.path = c->cfg.path;
   p.tuned = tuned;
   if (tuned == 0) {
@@ -835,7 +836,7 @@ emagpie_status emagpie_plan_describe(int32_t m, int32_t fft_plan, int32_t finali
   emagpie_plan p{};
   if (!emg::fft_plan_desc(m, fft_plan, &p.r1, &p.r2, &p.threads))
     return fail(EMAGPIE_E_ARG, "no such FFT plan for this m");
-  if (!emg::fin_shape_desc(finalize_shape, &p.fin_threads, &p.fin_tile, &p.fin_banded))
+  if (!emg::fin_shape_desc(finalize_shape, &p.fin_threads, &p.fin_tile, &p.fin_order))
     return fail(EMAGPIE_E_ARG, "no such finalize shape");
   p.fft_plan = fft_plan;
   p.finalize_shape = finalize_shape;

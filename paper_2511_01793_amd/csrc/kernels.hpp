@@ -916,6 +916,8 @@ __global__ __launch_bounds__(FinShape<F>::FNT) void k_finalize(const int4* slot,
       const int q = ntiles / X, r = ntiles % X, x = item % X;
       item = x * q + min(x, r) + item / X;
     }
+  } else if constexpr (FinShape<F>::ORDER == 2) {
+    if (item < ntiles) item = rows_per_xcd_tile(item, ntiles, (n + T - 1) / T);
   }
   finalize_item<M, FNT, T>(a, item, ntiles, L, tid);
 }
@@ -1466,6 +1468,10 @@ hipError_t with_fin(int f, Fn&& fn) {
     case 5: return fn(IC<5>{});
     case 6: return fn(IC<6>{});
     case 7: return fn(IC<7>{});
+    case 8: return fn(IC<8>{});
+    case 9: return fn(IC<9>{});
+    case 10: return fn(IC<10>{});
+    case 11: return fn(IC<11>{});
     default: return hipErrorInvalidValue;
   }
 }

@@ -72,12 +72,18 @@ inline int fft_plan_count(int m) { return m == 32 ? 2 : m == 64 ? 4 : m == 128 ?
 
 // finalize shapes: (threads per item, object tile side) for F & 3, and the
 // order in which the grid's blocks take the object tiles for F >> 2: row-major
-// (0) or banded (1).  Block i of a launch runs on XCD i mod kDispatchXcds; banded,
-// XCD x takes the x-th contiguous band of tile rows, the band of the object whose
-// patches the same XCD ran when the minibatch was listed for the XCDs, so their
-// numerators may still be in its L2.  Which order is faster depends on how the
-// scan spreads the work (uniform rasters favour bands, a dense centre favours
-// row-major), so both are candidates for the autotuner.
+// (0), banded (1) or rows per XCD (2).  Block i of a launch runs on XCD
+// i mod kDispatchXcds.
+//  * banded: XCD x takes the x-th contiguous band of tile rows, the band of the
+//    object whose patches the same XCD ran when the minibatch was listed for the
+//    XCDs, so their numerators may still be in its L2;
+//  * rows per XCD: XCD x takes the tile rows x, x + 8, x + 16, ...: the tiles side
+//    by side in a row share the cache lines where a numerator row segment crosses
+//    from one tile into the next, and those lines are then fetched into one L2
+//    instead of two.
+// Which order is faster depends on how the scan spreads the work (uniform rasters
+// favour bands, a dense centre favours row-major or rows per XCD), so all are
+// candidates for the autotuner.  The order changes no result.
 constexpr int kDispatchXcds = 8;
 template <int F> struct FinShapeBase;
 template <> struct FinShapeBase<0> { static constexpr int FNT = 256, T = 32; };
@@ -85,17 +91,35 @@ template <> struct FinShapeBase<1> { static constexpr int FNT = 256, T = 16; };
 template <> struct FinShapeBase<2> { static constexpr int FNT = 512, T = 32; };
 template <> struct FinShapeBase<3> { static constexpr int FNT = 1024, T = 64; };
 template <int F> struct FinShape : FinShapeBase<F & 3> {
-  static constexpr bool BANDED = ((F >> 2) & 1) != 0;
+  static constexpr int ORDER = F >> 2;  // 0 row-major, 1 banded, 2 rows per XCD
+  static constexpr bool BANDED = ORDER == 1;
 };
-constexpr int kFinShapes = 8;
+constexpr int kFinShapes = 12;
 
-inline bool fin_shape_desc(int f, int* fnt, int* tile, int* banded = nullptr) {
+inline bool fin_shape_desc(int f, int* fnt, int* tile, int* order = nullptr) {
   static const int t[4][2] = {{256, 32}, {256, 16}, {512, 32}, {1024, 64}};
   if (f < 0 || f >= kFinShapes) return false;
   *fnt = t[f & 3][0];
   *tile = t[f & 3][1];
-  if (banded) *banded = (f >> 2) & 1;
+  if (order) *order = f >> 2;
   return true;
+}
+
+// Tile taken by block i < ntiles in the rows-per-XCD order (tpr tiles per tile row).
+// Blocks are listed XCD by XCD (block i is the (i / X)-th of XCD i mod X) and tiles
+// rows x, x + X, ... for x = 0, 1, ...; the i-th block in the first list takes the
+// tile at the same place in the second.  A bijection of [0, ntiles) for any sizes.
+__host__ __device__ inline int rows_per_xcd_tile(int i, int ntiles, int tpr) {
+  constexpr int X = kDispatchXcds;
+  const int x = i % X, trows = ntiles / tpr;
+  int pos = i / X;
+  for (int y = 0; y < x; ++y) pos += (ntiles - y + X - 1) / X;  // blocks on the XCDs before x
+  for (int y = 0; y < X; ++y) {
+    const int seg = ((trows - y + X - 1) / X) * tpr;  // tiles in the rows y, y + X, ...
+    if (pos < seg) return (y + X * (pos / tpr)) * tpr + pos % tpr;
+    pos -= seg;
+  }
+  return i;  // not reached for i < ntiles
 }
 
 // Slot groups of the probe sums in the finalize: each probe pixel's sum over

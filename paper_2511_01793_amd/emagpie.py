@@ -62,9 +62,9 @@ class Plan(ctypes.Structure):
     _fields_ = [
         ("fft_plan", ctypes.c_int32), ("r1", ctypes.c_int32), ("r2", ctypes.c_int32),
         ("threads", ctypes.c_int32), ("finalize_shape", ctypes.c_int32),
-        ("fin_threads", ctypes.c_int32), ("fin_tile", ctypes.c_int32), ("fin_banded", ctypes.c_int32),
+        ("fin_threads", ctypes.c_int32), ("fin_tile", ctypes.c_int32), ("fin_order", ctypes.c_int32),
         ("path", ctypes.c_int32), ("tuned", ctypes.c_int32), ("n_fft_plans", ctypes.c_int32),
-        ("fft_us", ctypes.c_float * 4), ("n_fin_shapes", ctypes.c_int32), ("fin_us", ctypes.c_float * 8),
+        ("fft_us", ctypes.c_float * 4), ("n_fin_shapes", ctypes.c_int32), ("fin_us", ctypes.c_float * 12),
         ("path_ms", ctypes.c_float * 8),
     ]
 
@@ -173,7 +173,7 @@ def plan_describe(m: int, fft_plan: int = 0, finalize_shape: int = 0) -> dict:
     p, cnt = Plan(), ctypes.c_int32(0)
     _check(lib().emagpie_plan_describe(m, fft_plan, finalize_shape, ctypes.byref(p), ctypes.byref(cnt)))
     d = {k: getattr(p, k) for k in ("fft_plan", "r1", "r2", "threads", "finalize_shape",
-                                    "fin_threads", "fin_tile", "fin_banded")}
+                                    "fin_threads", "fin_tile", "fin_order")}
     d["fft_plans"] = cnt.value
     return d
 

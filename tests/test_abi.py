@@ -103,24 +103,24 @@ def test_plan_descriptions_are_consistent(m):
     assert count >= 2
     splits = set()
     for v in range(count):
-        for f in range(8):
+        for f in range(12):
             d = E.plan_describe(m, v, f)
             assert d["r1"] * d["r2"] == m and d["r1"] in (4, 8, 16) and d["r2"] in (4, 8, 16)
             assert d["threads"] in (256, 512, 1024) and (m * m) % (4 * d["threads"]) == 0
             assert d["fin_tile"] ** 2 % d["fin_threads"] == 0 and d["fin_threads"] % 256 == 0
-            # shapes 4..7 are 0..3 with the banded tile order
+            # shapes 4..7 and 8..11 are 0..3 with the banded and the rows-per-XCD tile orders
             b = E.plan_describe(m, v, f % 4)
             assert (d["fin_threads"], d["fin_tile"]) == (b["fin_threads"], b["fin_tile"])
-            assert d["fin_banded"] == (f >= 4)
+            assert d["fin_order"] == f // 4
         splits.add((d["r1"], d["r2"]))
     assert len(splits) >= 2  # at least two radix splits to choose from
-    for bad_v, bad_f in [(count, 0), (-1, 0), (0, 8), (0, -1)]:
+    for bad_v, bad_f in [(count, 0), (-1, 0), (0, 12), (0, -1)]:
         with pytest.raises(E.EmagpieError) as ei:
             E.plan_describe(m, bad_v, bad_f)
         assert ei.value.name == "E_ARG"
 
 
-@pytest.mark.parametrize("bad", [dict(fft_plan=9), dict(fft_plan=-2), dict(finalize_shape=8),
+@pytest.mark.parametrize("bad", [dict(fft_plan=9), dict(fft_plan=-2), dict(finalize_shape=12),
                                  dict(finalize_shape=-3), dict(path=5), dict(m=32, fft_plan=2)])
 def test_plan_config_validation(bad):
     with pytest.raises(E.EmagpieError) as ei:
