@@ -221,7 +221,9 @@ emagpie_status emagpie_mg_cycle(emagpie_ctx ctx, const void* obj_dev, const void
  *   [2] Phi_B after the step (<= [1] by majorisation).
  * Prop. 3.2 guarantees [1] <= [0] for b = 1 and levels = 1.  Each value is an
  * FP64 sum, in a fixed order, of terms formed from FP32 state.  Uses the
- * plain-path kernels plus two reductions; it is meant for checking, not speed.
+ * plain-path kernels plus two reductions (at m = 256 the row-strip and
+ * column-block kernels, with the revised waves kept in the stack buffer); it is
+ * meant for checking, not speed.
  */
 emagpie_status emagpie_check_step(emagpie_ctx ctx, void* obj_dev, void* probe_dev,
                                   const int32_t* batch_idx_dev, int32_t b, double* out3_dev,
@@ -235,8 +237,10 @@ emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* 
  * Gradients of Phi (Sec. 2.1, CR calculus; gradient = d/dx + i d/dy):
  * grad_obj = sum_k P_k^T conj(Q)(Q z_k - R_k) (n_rows x n_cols), grad_probe = sum_k
  * conj(z_k)(Q z_k - R_k) (m x m), and Phi to misfit_dev.  dtype EMAGPIE_F32
- * takes complex64 obj/probe/gradients, EMAGPIE_F64 complex128 (m <= 64).
- * Gradients are overwritten, not accumulated.
+ * takes complex64 obj/probe/gradients (every m; at m = 256 the patterns go in
+ * chunks of the minibatch through the row-strip and column-block kernels),
+ * EMAGPIE_F64 complex128 (m <= 64; EMAGPIE_E_UNSUPPORTED otherwise).  Gradients
+ * are overwritten, not accumulated.
  */
 emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* probe_dev,
                             void* grad_obj_dev, void* grad_probe_dev, double* misfit_dev,

@@ -135,7 +135,8 @@ Layout make_layout(const emagpie_config& c) {
   L.scal = take(256);
   L.bar = take(256);
   L.phi_all = take(N * 8);
-  L.grad_chunk = c.m == 256 ? 0 : (int)std::min<size_t>(N, c.m == 128 ? 256 : emg::kMaxSlots);
+  // patterns per gradient chunk: at m = 256 the stack buffer's minibatch
+  L.grad_chunk = (int)std::min<size_t>(N, c.m == 256 ? B : c.m == 128 ? 256 : emg::kMaxSlots);
   const size_t gel = c.m <= 64 ? 16 : 8;  // complex128 where the float64 gradient exists
   L.gz = take((size_t)L.grad_chunk * m2 * gel);
   L.gq = take((size_t)L.grad_chunk * m2 * gel);
@@ -1071,10 +1072,17 @@ emagpie_status emagpie_check_step(emagpie_ctx ctx, void* obj_dev, void* probe_de
   if (!obj_dev || !probe_dev || !batch_idx_dev || !out3_dev)
     return fail(EMAGPIE_E_ARG, "null argument");
   if (b < 1 || b > ctx->cfg.minibatch) return fail(EMAGPIE_E_ARG, "b must be in [1, minibatch]");
-  if (ctx->cfg.m == 256) return fail(EMAGPIE_E_UNSUPPORTED, "no descent check for m = 256");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int m = ctx->cfg.m, v = ctx->cfg.fft_plan;
   EMG_HIP(emg::launch_slot_info(batch_idx_dev, ctx->pos, ctx->cfg.n_pos, ctx->slots, b, s));
+  if (m == 256) {
+    emg::StepArgs a = base_args(ctx, obj_dev, probe_dev);
+    a.slot = ctx->slots;
+    a.b = b;
+    EMG_HIP(emg::launch_zero_doubles(out3_dev, 3, s));
+    EMG_HIP(emg::launch_check256(a, ctx->cfg.levels, ctx->cfg.finalize_shape, out3_dev, s));
+    return EMAGPIE_OK;
+  }
   emg::StepArgs a = base_args(ctx, obj_dev, probe_dev);
   a.slot = ctx->slots;
   a.b = b;
@@ -1127,7 +1135,6 @@ emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* pr
   if (dtype != EMAGPIE_F32 && dtype != EMAGPIE_F64) return fail(EMAGPIE_E_ARG, "dtype must be F32 or F64");
   const bool f64 = dtype == EMAGPIE_F64;
   if (f64 && ctx->cfg.m > 64) return fail(EMAGPIE_E_UNSUPPORTED, "float64 gradient needs m <= 64");
-  if (ctx->cfg.m == 256) return fail(EMAGPIE_E_UNSUPPORTED, "no gradient for m = 256");
   hipStream_t s = static_cast<hipStream_t>(stream);
   emg::GradArgs g{};
   g.obj = obj_dev;
@@ -1144,7 +1151,12 @@ emagpie_status emagpie_grad(emagpie_ctx ctx, const void* obj_dev, const void* pr
   g.gz_slots = ctx->ws + ctx->lay.gz.off;
   g.gq_slots = ctx->ws + ctx->lay.gq.off;
   g.phi_all = ctx->phi_all;
-  EMG_HIP(emg::launch_grad(ctx->cfg.m, ctx->cfg.fft_plan, f64, g, s));
+  if (ctx->cfg.m == 256) {
+    const emg::StepArgs a = base_args(ctx, const_cast<void*>(obj_dev), const_cast<void*>(probe_dev));
+    EMG_HIP(emg::launch_grad256(a, g, s));
+  } else {
+    EMG_HIP(emg::launch_grad(ctx->cfg.m, ctx->cfg.fft_plan, f64, g, s));
+  }
   if (misfit_dev) EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
   return EMAGPIE_OK;
 }

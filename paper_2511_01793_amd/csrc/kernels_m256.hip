@@ -85,10 +85,15 @@ __global__ __launch_bounds__(256) void k256_rows_fwd(StepArgs a, int k0) {
   for (int r = 0; r < S; ++r) st(out, (size_t)r * M + tid, A[r * LSR + tid]);
 }
 
-// 2. column block cb of slot s: forward column passes, projection (STEP) or only
-// the misfit residual (!STEP), inverse column passes (STEP)
-template <bool STEP>
+// 2. column block cb of slot s: forward column passes, then in the pair pass the
+// modulus projection (kColsStep), only the misfit terms (kColsMisfit), or the Fourier
+// residual of the gradient (kColsGrad: Psi - Psi' = (|Psi| - a) Psi / |Psi|, or -a
+// where Psi = 0, scaled by 1/m^2, with the misfit terms of the gradient's own
+// arithmetic); inverse column passes (kColsStep, kColsGrad)
+constexpr int kColsMisfit = 0, kColsStep = 1, kColsGrad = 2;
+template <int MODE>
 __global__ __launch_bounds__(256) void k256_cols(StepArgs a, int k0) {
+  constexpr bool STEP = MODE == kColsStep, INVERSE = MODE != kColsMisfit;
   using namespace big;
   __shared__ cx<float> A[M * LSC];
   __shared__ cx<float> tws[M];
@@ -119,6 +124,13 @@ __global__ __launch_bounds__(256) void k256_cols(StepArgs a, int k0) {
     if constexpr (STEP) {
       float2* pe = ph ? ph + (size_t)(R1 * g + e) * M + col0 + line : nullptr;
       acc += (double)project_amp<M>(v, amplitude(amp[e]), pe, a.phase_write != 0);
+    } else if constexpr (MODE == kColsGrad) {
+      const float am = sqrtf(fmaxf(amp[e], 0.f));
+      const float mag = sqrtf(norm2(v));
+      const float diff = mag - am;
+      acc += (double)diff * (double)diff;
+      const cx<float> E = mag > 0.f ? scale(v, diff / mag) : cx<float>{-am, 0.f};
+      v = scale(E, 1.f / float(M * M));
     } else {
       cx<float> t = v;
       acc += (double)project_amp<M>(t, amplitude(amp[e]));
@@ -128,7 +140,7 @@ __global__ __launch_bounds__(256) void k256_cols(StepArgs a, int k0) {
   if ((tid & 63) == 0) redd[tid >> 6] = acc;
   __syncthreads();
   if (tid == 0) a.part_phi[s * S + cb] = lds_sum<NT>(redd);
-  if constexpr (STEP) {
+  if constexpr (INVERSE) {
     fft_pass_lines<float, M, R1, R2, S, NT, LSC, true, true, true>(A, tws, tid);
     __syncthreads();
 #pragma unroll
@@ -139,8 +151,10 @@ __global__ __launch_bounds__(256) void k256_cols(StepArgs a, int k0) {
   }
 }
 
-// 3. inverse row passes of strip rb of slot s and the strip's per-pixel algebra
-template <int L>
+// 3. inverse row passes of strip rb of slot s and the strip's per-pixel algebra;
+// with STORE_R the revised exit wave R_k of the strip also goes back to the stack
+// buffer (the descent check keeps it, frozen, for the surrogate after the step)
+template <int L, bool STORE_R = false>
 __global__ __launch_bounds__(256) void k256_rows_inv(StepArgs a) {
   using namespace big;
   __shared__ cx<float> A[S * LSR];
@@ -169,6 +183,11 @@ __global__ __launch_bounds__(256) void k256_rows_inv(StepArgs a) {
   __syncthreads();
   fft_pass_lines<float, M, R1, R2, S, NT, LSR, true, true, false>(A, tws, tid);
   __syncthreads();
+  if constexpr (STORE_R) {
+    float2* outR = a.stack + (size_t)s * M * M + (size_t)row0 * M;
+#pragma unroll
+    for (int r = 0; r < S; ++r) st(outR, (size_t)r * M + tid, A[r * LSR + tid]);
+  }
   const size_t n = (size_t)a.n;
   const float2* zwin = a.obj + (size_t)sl.y * n + sl.z;
   pixel_update_ly<M, StripLayout, L, false>(
@@ -186,14 +205,69 @@ __global__ __launch_bounds__(256) void k256_rows_inv(StepArgs a) {
       qqmax, zmax);
 }
 
-// per-pattern misfit terms from the column blocks' partial sums, in block order
+// per-pattern terms from the 16 partial sums of its column blocks (or strips), in
+// block order, times `scale`
 __global__ __launch_bounds__(256) void k256_phi_reduce(const double* part_phi, int count,
-                                                       double* phi_out) {
+                                                       double* phi_out, double scale) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
   double t = part_phi[i * big::S];
   for (int c = 1; c < big::S; ++c) t += part_phi[i * big::S + c];
-  phi_out[i] = t / (2.0 * big::M * big::M);
+  phi_out[i] = t * scale;
+}
+
+// gradient: inverse row passes of strip rb of pattern k0 + s turn the Fourier residual
+// into e_k = Q z_k - R_k; the strip's slot terms conj(Q) e_k (object) and conj(z_k) e_k
+// (probe) go to the gradient slots, for the shared reductions k_grad_scatter and
+// k_grad_probe
+__global__ __launch_bounds__(256) void k256_rows_grad(StepArgs a, int k0, float2* gz, float2* gq) {
+  using namespace big;
+  __shared__ cx<float> A[S * LSR];
+  __shared__ cx<float> tws[M];
+  const int tid = threadIdx.x, nsl = gridDim.x / S, s = blockIdx.x % nsl, rb = blockIdx.x / nsl,
+            row0 = rb * S;
+  const int2 p = a.pos[k0 + s];
+  tws[tid] = ld(a.tw, tid);
+  const float2* in = a.stack + (size_t)s * M * M + (size_t)row0 * M;
+#pragma unroll
+  for (int r = 0; r < S; ++r) A[r * LSR + tid] = ld(in, (size_t)r * M + tid);
+  __syncthreads();
+  fft_pass_lines<float, M, R1, R2, S, NT, LSR, true, false, false>(A, tws, tid);
+  __syncthreads();
+  fft_pass_lines<float, M, R1, R2, S, NT, LSR, true, true, false>(A, tws, tid);
+  __syncthreads();
+  const size_t n = (size_t)a.n, base = (size_t)s * M * M + (size_t)row0 * M;
+  const float2* zwin = a.obj + (size_t)(p.x + row0) * n + p.y;
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    const cx<float> ev = A[r * LSR + tid];
+    const cx<float> q = ld(a.probe, (size_t)(row0 + r) * M + tid);
+    const cx<float> zz = ld(zwin, (size_t)r * n + tid);
+    st(gz, base + (size_t)r * M + tid, cmulc(q, ev));
+    st(gq, base + (size_t)r * M + tid, cmulc(zz, ev));
+  }
+}
+
+// descent check: 1/2 ||Q . z_k - R_k||^2 (Eq. 3 with R_k frozen in the stack buffer) of
+// strip rb of slot s at the current state; FP32 differences, FP64 sum -> part_phi
+__global__ __launch_bounds__(256) void k256_surrogate_strips(StepArgs a) {
+  using namespace big;
+  __shared__ double redd[NT / 64];
+  const int tid = threadIdx.x, nsl = gridDim.x / S, s = blockIdx.x % nsl, rb = blockIdx.x / nsl,
+            row0 = rb * S;
+  const int4 sl = a.slot[s];
+  const size_t n = (size_t)a.n;
+  const float2* zwin = a.obj + (size_t)(sl.y + row0) * n + sl.z;
+  const float2* Rg = a.stack + (size_t)s * M * M + (size_t)row0 * M;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    const cx<float> d = sub(mul(ld(a.probe, (size_t)(row0 + r) * M + tid), ld(zwin, (size_t)r * n + tid)),
+                            ld(Rg, (size_t)r * M + tid));
+    acc += (double)d.re * (double)d.re + (double)d.im * (double)d.im;
+  }
+  const double tot = block_sum<NT>(acc, redd, tid);
+  if (tid == 0) a.part_phi[s * S + rb] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -206,7 +280,7 @@ hipError_t Launchers256::patch_step(int v, int L, const StepArgs& a, hipStream_t
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k256_rows_fwd, grid, block, 0, s, a, 0);
-  hipLaunchKernelGGL(k256_cols<true>, grid, block, 0, s, a, 0);
+  hipLaunchKernelGGL(k256_cols<kColsStep>, grid, block, 0, s, a, 0);
   switch (L) {
     case 1: hipLaunchKernelGGL(k256_rows_inv<1>, grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL(k256_rows_inv<2>, grid, block, 0, s, a); break;
@@ -224,10 +298,67 @@ hipError_t Launchers256::misfit_strips(const StepArgs& a, int k0, int count, dou
   x.slot = nullptr;
   const dim3 grid(count * big::S), block(big::NT);
   hipLaunchKernelGGL(k256_rows_fwd, grid, block, 0, s, x, k0);
-  hipLaunchKernelGGL(k256_cols<false>, grid, block, 0, s, x, k0);
+  hipLaunchKernelGGL(k256_cols<kColsMisfit>, grid, block, 0, s, x, k0);
   hipLaunchKernelGGL(k256_phi_reduce, dim3((count + 255) / 256), dim3(256), 0, s,
-                     (const double*)x.part_phi, count, phi_out);
+                     (const double*)x.part_phi, count, phi_out, 1.0 / (2.0 * big::M * big::M));
   return hipGetLastError();
+}
+
+hipError_t launch_grad256(const StepArgs& a, const GradArgs& g, hipStream_t s) {
+  constexpr int M = 256, TS = kGradTile, PPU = 256 / kGradQGroups;
+  if (!a.part_q || g.chunk < 1) return hipErrorInvalidValue;
+  StepArgs x = a;
+  x.slot = nullptr;
+  const int tiles = ((g.nr + TS - 1) / TS) * ((g.n + TS - 1) / TS);
+  for (int k0 = 0; k0 < g.n_pos; k0 += g.chunk) {
+    const int cnt = min(g.chunk, g.n_pos - k0);
+    const dim3 grid(cnt * big::S), block(big::NT);
+    hipLaunchKernelGGL(k256_rows_fwd, grid, block, 0, s, x, k0);
+    hipLaunchKernelGGL(k256_cols<kColsGrad>, grid, block, 0, s, x, k0);
+    hipLaunchKernelGGL(k256_rows_grad, grid, block, 0, s, x, k0, static_cast<float2*>(g.gz_slots),
+                       static_cast<float2*>(g.gq_slots));
+    hipLaunchKernelGGL(k256_phi_reduce, dim3((cnt + 255) / 256), dim3(256), 0, s,
+                       (const double*)x.part_phi, cnt, g.phi_all + k0, 1.0 / (2.0 * M * M));
+    const int first = k0 == 0;
+    hipLaunchKernelGGL((k_grad_scatter<float, M>), dim3(tiles), dim3(256 * kGradZGroups), 0, s, g,
+                       k0, cnt, first);
+    hipLaunchKernelGGL((k_grad_probe<float, M>), dim3((M * M + PPU - 1) / PPU), dim3(256), 0, s, g,
+                       cnt, first);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_check256(const StepArgs& a, int levels, int finalize_shape, double* out3,
+                           hipStream_t s) {
+  if (!a.part_q || !a.slot || levels < 1 || levels > 3) return hipErrorInvalidValue;
+  const dim3 grid(a.b * big::S), block(big::NT);
+  // the step, keeping the revised waves R_k of the state before it in the stack buffer
+  hipLaunchKernelGGL(k256_rows_fwd, grid, block, 0, s, a, 0);
+  hipLaunchKernelGGL(k256_cols<kColsStep>, grid, block, 0, s, a, 0);
+  switch (levels) {
+    case 1: hipLaunchKernelGGL((k256_rows_inv<1, true>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k256_rows_inv<2, true>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k256_rows_inv<3, true>), grid, block, 0, s, a); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  StepArgs f = a;
+  f.sampled = out3;  // [0] += sum_k Phi_k at the state before the step
+  if ((e = Launchers256::finalize(finalize_shape, f, s, nullptr, nullptr)) != hipSuccess) return e;
+  // [1] surrogate of Eq. 3 at the new state against the frozen R_k
+  hipLaunchKernelGGL(k256_surrogate_strips, grid, block, 0, s, a);
+  hipLaunchKernelGGL(k256_phi_reduce, dim3((a.b + 255) / 256), dim3(256), 0, s,
+                     (const double*)a.part_phi, a.b, a.phi, 0.5);
+  if ((e = launch_sum_doubles(a.phi, a.b, out3 + 1, s)) != hipSuccess) return e;
+  // [2] Phi_B at the new state: the batch's misfit terms through the strip kernels
+  hipLaunchKernelGGL(k256_rows_fwd, grid, block, 0, s, a, 0);
+  hipLaunchKernelGGL(k256_cols<kColsMisfit>, grid, block, 0, s, a, 0);
+  hipLaunchKernelGGL(k256_phi_reduce, dim3((a.b + 255) / 256), dim3(256), 0, s,
+                     (const double*)a.part_phi, a.b, a.phi, 1.0 / (2.0 * big::M * big::M));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_sum_doubles(a.phi, a.b, out3 + 2, s);
 }
 
 hipError_t Launchers256::finalize(int f, const StepArgs& a, hipStream_t s, hipEvent_t e0,

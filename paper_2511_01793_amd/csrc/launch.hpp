@@ -137,6 +137,15 @@ hipError_t launch_grad(int m, int v, bool f64, const GradArgs& g, hipStream_t s)
 
 // m = 256 misfit terms of patterns k0 .. k0 + count - 1 (count <= the context's
 // minibatch; uses a.stack and the part_* buffers) -> phi_out[0 .. count)
+// m = 256 gradient: chunks of g.chunk patterns (<= the context's minibatch) through the
+// strip and column-block kernels over a.stack and a.part_*, then the shared reductions
+hipError_t launch_grad256(const StepArgs& a, const GradArgs& g, hipStream_t s);
+// m = 256 descent check of the minibatch a.slot / a.b: the step (revised waves kept in
+// a.stack), the finalize, then out3[1] (surrogate) and out3[2] (Phi_B after); out3 zeroed
+// by the caller, out3[0] accumulated by the finalize
+hipError_t launch_check256(const StepArgs& a, int levels, int finalize_shape, double* out3,
+                           hipStream_t s);
+
 hipError_t launch_misfit_strips(int m, const StepArgs& a, int k0, int count, double* phi_out,
                                 hipStream_t s);
 

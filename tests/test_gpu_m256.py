@@ -1,5 +1,6 @@
-"""Probe side m = 256 (row strips and column blocks over the stack buffer) against the oracle,
-and the requests this size does not support."""
+"""Probe side m = 256 (row strips and column blocks over the stack buffer) against the oracle:
+steps, epochs, mg_cycle, the phase memory, the adjoint gradient and the descent check; and the
+requests this size does not support."""
 import numpy as np
 import pytest
 
@@ -131,9 +132,72 @@ def test_m256_unsupported_requests_are_rejected():
         assert ei.value.name == "E_UNSUPPORTED"
     rec = make_rec(p, path="fused")
     obj, probe = init_state(p, rec)
-    for call in (lambda: rec.grad(obj, probe), lambda: rec.check_step(obj, probe, [0]),
+    for call in (lambda: rec.grad(obj.to(torch.complex128), probe.to(torch.complex128)),
                  lambda: E.Group([rec])):
         with pytest.raises(E.EmagpieError) as ei:
             call()
         assert ei.value.name == "E_UNSUPPORTED"
     rec.close()
+
+
+# ------------------------------------------------------------------ gradient (Sec. 2.1)
+
+@pytest.mark.parametrize("B", [4, 3])
+def test_m256_gradient_parity(B):
+    # 9 patterns in chunks of the minibatch (4: chunks 4, 4, 1; 3: three of 3), so later chunks
+    # add onto the first
+    from gpu_helpers import GRAD32_TOL
+    p = big(L=1, B=B, seed=85)
+    say("case: m256 grad", B)
+    rec = make_rec(p, path="fused")
+    obj, probe = init_state(p, rec)
+    rec.epoch(obj, probe, 3)
+    gz, gq, phi = rec.grad(obj, probe)
+    torch.cuda.synchronize()
+    rz, rq, rphi = O.gradients(host(probe), host(obj), p.positions, amps(p))
+    assert rel(host(gz), rz) < GRAD32_TOL, rel(host(gz), rz)
+    assert rel(host(gq), rq) < GRAD32_TOL, rel(host(gq), rq)
+    assert abs(float(phi.item()) - rphi) <= MISFIT_TOL * rphi
+    # the misfit of the gradient call agrees with the misfit call
+    assert abs(float(phi.item()) - float(rec.misfit(obj, probe).item())) <= MISFIT_TOL * rphi
+    rec.close()
+
+
+# ------------------------------------------------------------------ descent check (Eq. 3)
+
+@pytest.mark.parametrize("L, idx", [(1, [5]), (2, [4, 0, 7])])
+def test_m256_check_step(L, idx):
+    # the three FP64 values against the oracle's misfit and surrogate at the same states, the
+    # step bitwise the plain step, majorisation, and Prop. 3.2's descent for one position and
+    # one level
+    p = big(L=L, B=4, seed=87)
+    say("case: m256 check", L, idx)
+    a = amps(p)
+    recs, states = [], []
+    for _ in range(2):
+        rec = make_rec(p, path="fused")
+        obj, probe = init_state(p, rec)
+        rec.epoch(obj, probe, 2)
+        recs.append(rec)
+        states.append((obj, probe))
+    torch.cuda.synchronize()
+    (o1, q1), (o2, q2) = states
+    z0, qq0 = host(o1), host(q1)
+    out = recs[0].check_step(o1, q1, idx)
+    recs[1].step(o2, q2, idx)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2) and torch.equal(q1, q2)
+    v = out.cpu().numpy()
+    sel = [p.positions[k] for k in idx]
+    before = O.misfit(qq0, z0, sel, a[idx])
+    R = [O.revised_exit_wave(qq0, z0[r:r + 256, c:c + 256], a[k]) for k, (r, c) in zip(idx, sel)]
+    after_sur = O.surrogate(host(q1), host(o1), sel, R)
+    after = O.misfit(host(q1), host(o1), sel, a[idx])
+    assert abs(v[0] - before) <= MISFIT_TOL * before
+    assert abs(v[1] - after_sur) <= MISFIT_TOL * max(after_sur, 1e-30)
+    assert abs(v[2] - after) <= MISFIT_TOL * max(after, 1e-30)
+    assert v[2] <= v[1] * (1 + 1e-6)  # majorisation
+    if L == 1 and len(idx) == 1:
+        assert v[1] <= v[0]  # Prop. 3.2
+    for r in recs:
+        r.close()
