@@ -214,9 +214,19 @@ struct PxLayout {
   __device__ static void origin(int tid, int rd, int& r0, int& c0) { blk_origin<M, V>(tid, rd, r0, c0); }
 };
 
-template <int M, class LY, int L, bool DIRECT, class LOAD>
-__device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int tid, int row0,
-                                                LOAD load, float qqmax, float zmax) {
+// Reciprocal of the coarse correction's divisors: the hardware approximation
+// (within one ulp, one instruction) instead of a correctly rounded division (about
+// ten).  The quotients only set the size of a correction that the step then weighs
+// against u, so a last-bit difference is immaterial to it.  A divisor below the
+// smallest normal float counts as zero (no correction), so the approximation never
+// sees a subnormal input.
+constexpr float kCoarseTiny = 1.17549435e-38f;  // FLT_MIN
+__device__ __forceinline__ float coarse_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ZP: the launch writes MAGPIE's z+ (a.zplus) instead of the numerators
+template <int M, class LY, int L, bool DIRECT, bool ZP, class LOAD>
+__device__ __forceinline__ void pixel_update_body(const StepArgs& a, int s, int tid, int row0,
+                                                  LOAD& load, float qqmax, float zmax) {
   const size_t base = (size_t)s * M * M;
   const bool slot_den = a.pden_slot != nullptr;
 #pragma unroll
@@ -251,16 +261,17 @@ __device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int ti
       }
     }
     // coarse correction of this 2 x 2 block: block-ratio form of the restricted
-    // coarse solve; three levels recurse once more over the 4 x 4 region
+    // coarse solve; three levels recurse once more over the 4 x 4 region.  Its
+    // quotients use the hardware reciprocal (coarse_rcp)
     cx<float> cc{0.f, 0.f};
     if constexpr (L == 2) {
-      if (Ds > 0.f) cc = scale(Gs, 1.f / Ds);
+      if (Ds >= kCoarseTiny) cc = scale(Gs, coarse_rcp(Ds));
     } else if constexpr (L == 3) {
-      const float w = Q2s > 0.f ? norm2(Qs) / (4.f * Q2s) : 0.f;
+      const float w = Q2s >= kCoarseTiny ? norm2(Qs) * coarse_rcp(4.f * Q2s) : 0.f;
       const cx<float> G2{quad_sum(w * Gs.re), quad_sum(w * Gs.im)};
       const float D2 = quad_sum(w * Ds);
-      const cx<float> c2 = D2 > 0.f ? scale(G2, 1.f / D2) : cx<float>{0.f, 0.f};
-      if (Ds > 0.f) cc = scale(axpy(Us, c2, Gs), 1.f / Ds);
+      const cx<float> c2 = D2 >= kCoarseTiny ? scale(G2, coarse_rcp(D2)) : cx<float>{0.f, 0.f};
+      if (Ds >= kCoarseTiny) cc = scale(axpy(Us, c2, Gs), coarse_rcp(Ds));
     }
     // numerators N = conj(Q) R + u z', M = conj(z) R + u_z Q and denominators
     cx<float> N[4], Mn[4];
@@ -269,7 +280,7 @@ __device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int ti
     for (int e = 0; e < 4; ++e) {
       const cx<float> zp = add(zz[e], cc);
       N[e] = axpy(u[e], zp, cqR[e]);
-      if (a.zplus) {
+      if constexpr (ZP) {
         N[e] = D[e] > 0.f ? scale(N[e], 1.f / D[e]) : zp;
       } else {
         const float z2 = norm2(zz[e]);
@@ -302,7 +313,7 @@ __device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int ti
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const size_t o = base + (size_t)(r0 + i) * M + c0;
-      if (a.zplus) {
+      if constexpr (ZP) {
         st_pair(a.zplus, o, N[2 * i], N[2 * i + 1]);
       } else {
         st_pair(a.numer, o, N[2 * i], N[2 * i + 1]);
@@ -315,7 +326,18 @@ __device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int ti
     }
   }
   // alpha_z = 1: the probe denominator |z_k|^2 + u_z = max |z_k|^2 is one number per patch
-  if (!DIRECT && slot_den && !a.zplus && tid == 0) a.pden_slot[s] = zmax;
+  if (!DIRECT && !ZP && slot_den && tid == 0) a.pden_slot[s] = zmax;
+}
+
+// The z+ output is a uniform choice: each case has a copy of the loop, so neither
+// tests it per pixel (the minibatch-1 update of DIRECT never writes z+).
+template <int M, class LY, int L, bool DIRECT, class LOAD>
+__device__ __forceinline__ void pixel_update_ly(const StepArgs& a, int s, int tid, int row0,
+                                                LOAD load, float qqmax, float zmax) {
+  if (!DIRECT && a.zplus)
+    pixel_update_body<M, LY, L, false, true>(a, s, tid, row0, load, qqmax, zmax);
+  else
+    pixel_update_body<M, LY, L, DIRECT, false>(a, s, tid, row0, load, qqmax, zmax);
 }
 
 template <int M, int V, int L, bool DIRECT = false, class LOAD>
@@ -432,7 +454,10 @@ __device__ __forceinline__ void xl_stage_amps(float* ampl, const float* ampv, in
 // of a dimension; waves 8..15 meanwhile
 // put the pattern's amplitudes in LDS in the column phase's order.  The sampled
 // misfit sums the same per-pixel terms as the LDS plans, in another order.
-template <int M, int V, int L, bool DIRECT = false, bool STAGE = false>
+//
+// PH = false: the context keeps no phase memory (a.phase is null), and the
+// projection is compiled without it; PH = true tests a.phase at run time.
+template <int M, int V, int L, bool DIRECT = false, bool STAGE = false, bool PH = true>
 __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>* A,
                                            cx<float>* tws, float* redf, double* redd,
                                            int tid) {
@@ -537,12 +562,16 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
       // forward column passes, projection, inverse column passes; each lane
       // writes back the elements it read
       xl_cols_forward(A, w, C, gi, v);
-      float2* ph = a.phase ? a.phase + (size_t)k * M * M : nullptr;
+      if (PH && a.phase) {
+        float2* ph = a.phase + (size_t)k * M * M;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        float2* pe = ph ? ph + (8 * gi + j) * M + C : nullptr;
-        acc += (double)project_amp<M>(v[j], ampl[(8 * gi + j) * (M + 1) + C], pe,
-                                      a.phase_write != 0);
+        for (int j = 0; j < 8; ++j)
+          acc += (double)project_amp<M>(v[j], ampl[(8 * gi + j) * (M + 1) + C],
+                                        ph + (8 * gi + j) * M + C, a.phase_write != 0);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          acc += (double)project_amp<M>(v[j], ampl[(8 * gi + j) * (M + 1) + C]);
       }
       dft8<float, true>(v);
       xl_transpose8(v);
@@ -576,14 +605,18 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
     __syncthreads();
     if constexpr (AS == 3) load_amps();
     // last forward pass, modulus projection, first inverse pass, in registers
-    float2* ph = a.phase ? a.phase + (size_t)k * M * M : nullptr;
+    float2* ph = (PH && a.phase) ? a.phase + (size_t)k * M * M : nullptr;
     fft_pass_pair<float, M, V>(A, tid, [&](int e, cx<float>& v) {
-      float2* pe = nullptr;
-      if (ph) {
-        const int w = tid + (e / CP::R1) * CP::NT;
-        pe = ph + (CP::R1 * (w / M) + e % CP::R1) * M + w % M;
+      if constexpr (PH) {
+        float2* pe = nullptr;
+        if (ph) {
+          const int w = tid + (e / CP::R1) * CP::NT;
+          pe = ph + (CP::R1 * (w / M) + e % CP::R1) * M + w % M;
+        }
+        acc += (double)project_amp<M>(v, amplitude(amp[e]), pe, a.phase_write != 0);
+      } else {
+        acc += (double)project_amp<M>(v, amplitude(amp[e]));
       }
-      acc += (double)project_amp<M>(v, amplitude(amp[e]), pe, a.phase_write != 0);
     });
     acc = wave_sum(acc);
     if ((tid & 63) == 0) redd[tid >> 6] = acc;
@@ -862,7 +895,7 @@ __device__ __forceinline__ void stage_twiddles(const float2* tw, cx<float>* tws,
 // in scalar registers at dispatch, so a kernel's first slot and object loads do
 // not wait for a load of its argument record (the record's fields are loaded
 // beside them).
-template <int M, int V, int L>
+template <int M, int V, int L, bool PH>
 __global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step(const int4* slot, float2* obj,
                                                                  int n, StepArgs rec) {
   StepArgs a = rec;
@@ -874,7 +907,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step(const int4* slo
   __shared__ float redf[32];
   __shared__ double redd[16];
   const int tid = threadIdx.x;
-  patch_step<M, V, L, false, true>(a, blockIdx.x, A, tws, redf, redd, tid);
+  patch_step<M, V, L, false, true, PH>(a, blockIdx.x, A, tws, redf, redd, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -883,7 +916,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step(const int4* slo
 // instance keeps its own state, data and workspace, so the arithmetic is the
 // single-instance arithmetic
 // ---------------------------------------------------------------------------
-template <int M, int V, int L>
+template <int M, int V, int L, bool PH>
 __global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step_multi(const StepArgs* args,
                                                                      const int2* work) {
   __shared__ cx<float> A[M * lds_stride<M>()];
@@ -893,7 +926,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_patch_step_multi(const Ste
   const int tid = threadIdx.x;
   const int2 w = work[blockIdx.x];
   const StepArgs a = args[w.x];
-  patch_step<M, V, L, false, true>(a, w.y, A, tws, redf, redd, tid);
+  patch_step<M, V, L, false, true, PH>(a, w.y, A, tws, redf, redd, tid);
 }
 
 template <int M, int F>
@@ -965,7 +998,7 @@ __device__ __forceinline__ void grid_barrier(unsigned* ctr, unsigned target, int
 }
 
 // persistent epoch: every minibatch of a sweep in one cooperative launch
-template <int M, int V, int L>
+template <int M, int V, int L, bool PH>
 __global__ __launch_bounds__((Plan<M, V>::NT)) void k_epoch_persistent(StepArgs a, int n_pos, int B,
                                                                      int ntiles, int nitems,
                                                                      unsigned* bar,
@@ -987,7 +1020,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_epoch_persistent(StepArgs 
     x.slot = slots + start;
     x.b = min(B, n_pos - start);
     for (int s = blockIdx.x; s < x.b; s += gridDim.x)
-      patch_step<M, V, L>(x, s, A, tws, redf, redd, tid);
+      patch_step<M, V, L, false, false, PH>(x, s, A, tws, redf, redd, tid);
     target += gridDim.x;
     grid_barrier(bar, target, err, spin_limit);
     for (int item = blockIdx.x; item < nitems; item += gridDim.x)
@@ -1002,7 +1035,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_epoch_persistent(StepArgs 
 // synchronisation: every step touches only its own window and the probe, and the
 // workgroup barrier at the end of each step orders it before the next.  The
 // sampled misfit accumulates exactly as the finalize adds it.
-template <int M, int V, int L>
+template <int M, int V, int L, bool PH>
 __global__ __launch_bounds__((Plan<M, V>::NT)) void k_sweep_chain(StepArgs a, int n_steps) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
@@ -1019,7 +1052,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_sweep_chain(StepArgs a, in
     StepArgs x = a;
     x.slot = slots + step;
     x.b = 1;
-    const double phi = patch_step<M, V, L, true>(x, 0, A, tws, redf, redd, tid);
+    const double phi = patch_step<M, V, L, true, false, PH>(x, 0, A, tws, redf, redd, tid);
     double t = 0.0;
     t += phi;
     sampled += t;
@@ -1447,6 +1480,13 @@ hipError_t with_plan(int v, Fn&& fn) {
   return hipErrorInvalidValue;
 }
 
+// PH of the patch kernels: compiled without the phase memory when a.phase is null
+template <class Fn>
+hipError_t with_phase(const StepArgs& a, Fn&& fn) {
+  if (a.phase) return fn(std::true_type{});
+  return fn(std::false_type{});
+}
+
 template <class Fn>
 hipError_t with_levels(int L, Fn&& fn) {
   switch (L) {
@@ -1483,19 +1523,22 @@ hipError_t Launchers<M>::patch_step(int v, int L, const StepArgs& a, hipStream_t
                                     hipEvent_t e1) {
   return with_plan<M>(v, [&](auto vc) {
     return with_levels(L, [&](auto lc) {
-      constexpr int V = decltype(vc)::value, LV = decltype(lc)::value, NT = Plan<M, V>::NT;
-      if (e0) {
-        StepArgs aa = a;
-        const int4* sl = a.slot;
-        float2* ob = a.obj;
-        int n = a.n;
-        void* args[] = {&sl, &ob, &n, &aa};
-        return hipExtLaunchKernel((const void*)k_patch_step<M, V, LV>, dim3(a.b), dim3(NT), args,
-                                  0, s, e0, e1, 0);
-      }
-      hipLaunchKernelGGL((k_patch_step<M, V, LV>), dim3(a.b), dim3(NT), 0, s, a.slot, a.obj, a.n,
-                         a);
-      return hipGetLastError();
+      return with_phase(a, [&](auto pc) {
+        constexpr int V = decltype(vc)::value, LV = decltype(lc)::value, NT = Plan<M, V>::NT;
+        constexpr bool PH = decltype(pc)::value;
+        if (e0) {
+          StepArgs aa = a;
+          const int4* sl = a.slot;
+          float2* ob = a.obj;
+          int n = a.n;
+          void* args[] = {&sl, &ob, &n, &aa};
+          return hipExtLaunchKernel((const void*)k_patch_step<M, V, LV, PH>, dim3(a.b), dim3(NT),
+                                    args, 0, s, e0, e1, 0);
+        }
+        hipLaunchKernelGGL((k_patch_step<M, V, LV, PH>), dim3(a.b), dim3(NT), 0, s, a.slot, a.obj,
+                           a.n, a);
+        return hipGetLastError();
+      });
     });
   });
 }
@@ -1528,8 +1571,9 @@ hipError_t Launchers<M>::patch_step_multi(int v, int L, const StepArgs* args, co
   return with_plan<M>(v, [&](auto vc) {
     return with_levels(L, [&](auto lc) {
       constexpr int V = decltype(vc)::value, LV = decltype(lc)::value;
-      hipLaunchKernelGGL((k_patch_step_multi<M, V, LV>), dim3(blocks), dim3(Plan<M, V>::NT), 0, s,
-                         args, work);
+      // the records live on the device: the phase memory is tested per instance
+      hipLaunchKernelGGL((k_patch_step_multi<M, V, LV, true>), dim3(blocks), dim3(Plan<M, V>::NT),
+                         0, s, args, work);
       return hipGetLastError();
     });
   });
@@ -1577,11 +1621,15 @@ hipError_t Launchers<M>::persistent_grid_size(int v, int L, int num_cus, int* gr
   return with_plan<M>(v, [&](auto vc) {
     return with_levels(L, [&](auto lc) {
       constexpr int V = decltype(vc)::value, LV = decltype(lc)::value;
-      int per = 0;
+      // the smaller of the two forms' residencies, so either launch fits
+      int per0 = 0, per1 = 0;
       hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, k_epoch_persistent<M, V, LV>, Plan<M, V>::NT, 0);
+          &per0, k_epoch_persistent<M, V, LV, false>, Plan<M, V>::NT, 0);
+      if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per1, k_epoch_persistent<M, V, LV, true>, Plan<M, V>::NT, 0);
       if (e != hipSuccess) return e;
-      *grid = per * num_cus;
+      *grid = min(per0, per1) * num_cus;
       return hipSuccess;
     });
   });
@@ -1606,8 +1654,9 @@ hipError_t Launchers<M>::persistent_epoch(int v, int L, const StepArgs& a, int n
       const int g = max(1, min(grid, want));
       *used_grid = g;
       void* args[] = {&aa, &np, &bb, &ntiles, &nitems, &br, &bb0, &er, &sl};
-      return hipLaunchCooperativeKernel((const void*)k_epoch_persistent<M, V, LV>, dim3(g),
-                                        dim3(NT), args, 0, s);
+      const void* fn = a.phase ? (const void*)k_epoch_persistent<M, V, LV, true>
+                               : (const void*)k_epoch_persistent<M, V, LV, false>;
+      return hipLaunchCooperativeKernel(fn, dim3(g), dim3(NT), args, 0, s);
     });
   });
 }
@@ -1677,10 +1726,12 @@ template <int M>
 hipError_t Launchers<M>::chain(int v, int L, const StepArgs& a, int n_steps, hipStream_t s) {
   return with_plan<M>(v, [&](auto vc) {
     return with_levels(L, [&](auto lc) {
-      constexpr int V = decltype(vc)::value, LV = decltype(lc)::value;
-      hipLaunchKernelGGL((k_sweep_chain<M, V, LV>), dim3(1), dim3(Plan<M, V>::NT), 0, s, a,
-                         n_steps);
-      return hipGetLastError();
+      return with_phase(a, [&](auto pc) {
+        constexpr int V = decltype(vc)::value, LV = decltype(lc)::value;
+        hipLaunchKernelGGL((k_sweep_chain<M, V, LV, decltype(pc)::value>), dim3(1),
+                           dim3(Plan<M, V>::NT), 0, s, a, n_steps);
+        return hipGetLastError();
+      });
     });
   });
 }
