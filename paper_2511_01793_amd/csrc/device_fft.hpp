@@ -469,20 +469,18 @@ __device__ __forceinline__ void fft2_inverse(cx<T>* A, const cx<T>* tw, int tid)
 
 // Principal complex square root (W. Kahan, "Branch Cuts for Complex
 // Elementary Functions", 1987: t = sqrt((|x| + |w|)/2), the other part from
-// y / (2t)), then the sign chosen so Re(root * conj(ref)) >= 0 (Eq. 6).
-template <typename T>
-__device__ __forceinline__ cx<T> aligned_sqrt(cx<T> ref, cx<T> plus) {
-  cx<T> w = mul(ref, plus);
-  T mag = sqrt(w.re * w.re + w.im * w.im);
-  if (mag == T(0)) return cx<T>{T(0), T(0)};
-  T t = sqrt((fabs(w.re) + mag) * T(0.5));
-  cx<T> s;
-  if (w.re >= T(0)) {
-    s = cx<T>{t, w.im / (T(2) * t)};
-  } else {
-    s = cx<T>{fabs(w.im) / (T(2) * t), copysign(t, w.im)};
-  }
-  if (s.re * ref.re + s.im * ref.im < T(0)) s = cx<T>{-s.re, -s.im};
+// y / (2t)), then the sign chosen so Re(root * conj(ref)) >= 0 (Eq. 6).  The
+// square roots and the reciprocal are the hardware's (within one ulp each).  A
+// product of modulus below 2^-125 (whose root is below 1.5e-19) gives 0; past that
+// test the second root and the reciprocal always take normal inputs.
+__device__ __forceinline__ cx<float> aligned_sqrt(cx<float> ref, cx<float> plus) {
+  const cx<float> w = mul(ref, plus);
+  const float mag = __builtin_amdgcn_sqrtf(w.re * w.re + w.im * w.im);
+  if (mag < 2.35098870e-38f) return cx<float>{0.f, 0.f};
+  const float t = __builtin_amdgcn_sqrtf((fabsf(w.re) + mag) * 0.5f);
+  const float h = 0.5f * __builtin_amdgcn_rcpf(t);  // 1 / (2 t)
+  cx<float> s = w.re >= 0.f ? cx<float>{t, w.im * h} : cx<float>{fabsf(w.im) * h, copysignf(t, w.im)};
+  if (s.re * ref.re + s.im * ref.im < 0.f) s = cx<float>{-s.re, -s.im};
   return s;
 }
 

@@ -214,14 +214,14 @@ struct PxLayout {
   __device__ static void origin(int tid, int rd, int& r0, int& c0) { blk_origin<M, V>(tid, rd, r0, c0); }
 };
 
-// Reciprocal of the coarse correction's divisors: the hardware approximation
-// (within one ulp, one instruction) instead of a correctly rounded division (about
-// ten).  The quotients only set the size of a correction that the step then weighs
-// against u, so a last-bit difference is immaterial to it.  A divisor below the
-// smallest normal float counts as zero (no correction), so the approximation never
-// sees a subnormal input.
-constexpr float kCoarseTiny = 1.17549435e-38f;  // FLT_MIN
-__device__ __forceinline__ float coarse_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Quotients of the step (the coarse correction's, z+ = N / D and Q+ = M / E) use the
+// hardware reciprocal (within one ulp, one instruction) instead of a correctly rounded
+// division (about ten).  A last-bit difference in a quotient is far below the step's
+// own FP32 rounding.  A divisor below the smallest normal float counts as zero (no
+// correction, the pixel left as it was), so the approximation never sees a subnormal
+// input.  Every path applies the same arithmetic, so they stay bitwise identical.
+constexpr float kMinDivisor = 1.17549435e-38f;  // FLT_MIN
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ZP: the launch writes MAGPIE's z+ (a.zplus) instead of the numerators
 template <int M, class LY, int L, bool DIRECT, bool ZP, class LOAD>
@@ -265,13 +265,13 @@ __device__ __forceinline__ void pixel_update_body(const StepArgs& a, int s, int 
     // quotients use the hardware reciprocal (coarse_rcp)
     cx<float> cc{0.f, 0.f};
     if constexpr (L == 2) {
-      if (Ds >= kCoarseTiny) cc = scale(Gs, coarse_rcp(Ds));
+      if (Ds >= kMinDivisor) cc = scale(Gs, hw_rcp(Ds));
     } else if constexpr (L == 3) {
-      const float w = Q2s >= kCoarseTiny ? norm2(Qs) * coarse_rcp(4.f * Q2s) : 0.f;
+      const float w = Q2s >= kMinDivisor ? norm2(Qs) * hw_rcp(4.f * Q2s) : 0.f;
       const cx<float> G2{quad_sum(w * Gs.re), quad_sum(w * Gs.im)};
       const float D2 = quad_sum(w * Ds);
-      const cx<float> c2 = D2 >= kCoarseTiny ? scale(G2, coarse_rcp(D2)) : cx<float>{0.f, 0.f};
-      if (Ds >= kCoarseTiny) cc = scale(axpy(Us, c2, Gs), coarse_rcp(Ds));
+      const cx<float> c2 = D2 >= kMinDivisor ? scale(G2, hw_rcp(D2)) : cx<float>{0.f, 0.f};
+      if (Ds >= kMinDivisor) cc = scale(axpy(Us, c2, Gs), hw_rcp(Ds));
     }
     // numerators N = conj(Q) R + u z', M = conj(z) R + u_z Q and denominators
     cx<float> N[4], Mn[4];
@@ -281,7 +281,7 @@ __device__ __forceinline__ void pixel_update_body(const StepArgs& a, int s, int 
       const cx<float> zp = add(zz[e], cc);
       N[e] = axpy(u[e], zp, cqR[e]);
       if constexpr (ZP) {
-        N[e] = D[e] > 0.f ? scale(N[e], 1.f / D[e]) : zp;
+        N[e] = D[e] >= kMinDivisor ? scale(N[e], hw_rcp(D[e])) : zp;
       } else {
         const float z2 = norm2(zz[e]);
         const float uz = a.alpha_z * (zmax - z2);
@@ -296,14 +296,14 @@ __device__ __forceinline__ void pixel_update_body(const StepArgs& a, int s, int 
       for (int e = 0; e < 4; ++e) {
         const int r = r0 + (e >> 1), c = c0 + (e & 1);
         const float dd = 0.f + D[e];
-        if (dd > 0.f) {
-          const cx<float> zp = scale(add(zero, N[e]), 1.f / dd);
+        if (dd >= kMinDivisor) {
+          const cx<float> zp = scale(add(zero, N[e]), hw_rcp(dd));
           st(a.obj, (size_t)(sl.y + r) * a.n + sl.z + c, a.joint ? aligned_sqrt(zz[e], zp) : zp);
         }
         if (a.update_probe) {
           const float et = 0.f + (slot_den ? zmax : E[e]);
-          if (et > 0.f) {
-            const cx<float> qp = scale(add(zero, Mn[e]), 1.f / et);
+          if (et >= kMinDivisor) {
+            const cx<float> qp = scale(add(zero, Mn[e]), hw_rcp(et));
             st(a.probe, (size_t)r * M + c, a.joint ? aligned_sqrt(q[e], qp) : qp);
           }
         }
@@ -803,9 +803,9 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
     for (int e = 0; e < PER; ++e) {
       const int q = tid + e * FNT;
       const int y = ty + q / T, x = tx + q % T;
-      if (accd[e] > 0.f && y < nr && x < n) {
+      if (accd[e] >= kMinDivisor && y < nr && x < n) {
         const size_t o = (size_t)y * n + x;
-        const cx<float> zp = scale(accn[e], 1.f / accd[e]);
+        const cx<float> zp = scale(accn[e], hw_rcp(accd[e]));
         st(a.obj, o, a.joint ? aligned_sqrt(zold[e], zp) : zp);
       }
     }
@@ -854,8 +854,8 @@ __device__ __forceinline__ void finalize_item(const StepArgs& a, int item, int n
         mt = add(mt, ld(L.pm, lp + k * ppu));
         et += L.pe[lp + k * ppu];
       }
-      if (et > 0.f) {
-        const cx<float> qp = scale(mt, 1.f / et);
+      if (et >= kMinDivisor) {
+        const cx<float> qp = scale(mt, hw_rcp(et));
         st(a.probe, r, a.joint ? aligned_sqrt(qold, qp) : qp);
       }
     }
