@@ -470,7 +470,7 @@ def bench_epochs(workload, K, W, args, p=None):
         unit_desc = f"one epoch ({len(U)} minibatches)"
     else:
         ms, cnt = prof["patch"]
-        kname = (f"k_patch_step<{m}, {bv}, {p.levels}>" if m < 256 else
+        kname = (f"k_patch_step<{m}, {bv}, {p.levels}, false>" if m < 256 else
                  f"k256_rows_fwd + k256_cols<true> + k256_rows_inv<{p.levels}>")
         bytes_per_launch = N * m * m * 12 / len(U)
         flops_per_launch = N * algorithmic_flops_pattern(m) / len(U)
@@ -480,6 +480,9 @@ def bench_epochs(workload, K, W, args, p=None):
     achieved = bytes_per_launch / avg_s / 1e9
     tflops = flops_per_launch / avg_s / 1e12
     traffic = None if persistent else recorded_traffic(workload, bv)
+    if traffic is not None:
+        # the counters were read on full minibatches; per average launch, like `achieved`
+        traffic *= (N / len(U)) / B
     log(f"[{workload}] dominant kernel {kname}: {avg_s * 1e6:.2f} us/launch, {achieved:.1f} GB/s, "
         f"{tflops:.1f} TFLOP/s; finalize {fms / max(fcnt, 1) * 1e3:.2f} us/launch")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
