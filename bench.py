@@ -63,11 +63,17 @@ KERNEL_SOURCES = ("device_fft.hpp", "plans.hpp", "kernels.hpp", "launch.hpp", "b
 
 
 def kernel_source_digest():
+    """Digest of the kernel sources' code: line comments (C++ `//`, Python `#`), trailing
+    blanks and empty lines are left out, so an edit of comments alone keeps it."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2511_01793_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        marker = "#" if name.endswith(".py") else "//"
+        with open(os.path.join(ROOT, "paper_2511_01793_amd", "csrc", name)) as f:
+            for line in f:
+                code = line.split(marker, 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

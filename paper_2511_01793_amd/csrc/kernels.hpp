@@ -261,8 +261,7 @@ __device__ __forceinline__ void pixel_update_body(const StepArgs& a, int s, int 
       }
     }
     // coarse correction of this 2 x 2 block: block-ratio form of the restricted
-    // coarse solve; three levels recurse once more over the 4 x 4 region.  Its
-    // quotients use the hardware reciprocal (coarse_rcp)
+    // coarse solve; three levels recurse once more over the 4 x 4 region
     cx<float> cc{0.f, 0.f};
     if constexpr (L == 2) {
       if (Ds >= kMinDivisor) cc = scale(Gs, hw_rcp(Ds));
