@@ -503,8 +503,54 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
     }
   };
   constexpr int AS = Plan<M, V>::AMP;
+  constexpr bool DG = Plan<M, V>::DG != 0;
+  static_assert(!DG || (!XL && !P::CACHE), "direct gather: LDS plans that reload per round");
+  if constexpr (DG) {
+    // The exit wave straight into the first (strided) row pass.  Item i = tid + it NT
+    // is row i / R1, group g = i % R1, points g + R1 j: the loads of one j cover
+    // 64 / R1 rows of a wave, R1 consecutive pixels of each.  The pass's twiddles
+    // W^(g j) come from the global table (cache-resident) with the other loads, so
+    // the pass runs before the first barrier.
+    constexpr int R1 = Plan<M, V>::R1, R2 = Plan<M, V>::R2, DIT = M * R1 / NT;
+    static_assert(DIT * NT == M * R1, "direct-gather items per thread");
+    cx<float> ps[DIT][R2], twr[DIT][R2];
+    {
+      cx<float> q[DIT][R2], zz[DIT][R2];
 #pragma unroll
-  for (int rd = 0; rd < R; ++rd) {
+      for (int it = 0; it < DIT; ++it) {
+        const int i = tid + it * NT, row = i / R1, g = i % R1;
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+          q[it][j] = ld(a.probe, (size_t)row * M + g + R1 * j);
+          zz[it][j] = ld(zwin, (size_t)row * n + g + R1 * j);
+        }
+#pragma unroll
+        for (int j = 1; j < R2; ++j) twr[it][j] = ld(a.tw, g * j);
+      }
+      if constexpr (AS == 0) load_amps();
+#pragma unroll
+      for (int it = 0; it < DIT; ++it) {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+          q2m = fmaxf(q2m, norm2(q[it][j]));
+          z2m = fmaxf(z2m, norm2(zz[it][j]));
+          ps[it][j] = mul(q[it][j], zz[it][j]);
+        }
+      }
+    }
+    // the strided pass as fft_pass computes it, then the tile to LDS
+#pragma unroll
+    for (int it = 0; it < DIT; ++it) {
+      const int i = tid + it * NT, row = i / R1, g = i % R1;
+      dft_small<float, false, R2, M>(ps[it], tws);
+#pragma unroll
+      for (int j = 1; j < R2; ++j) ps[it][j] = mul_fma(twr[it][j], ps[it][j]);
+#pragma unroll
+      for (int j = 0; j < R2; ++j) A[row * LS + g + R1 * j] = ps[it][j];
+    }
+  }
+#pragma unroll
+  for (int rd = 0; rd < (DG ? 0 : R); ++rd) {
     int r0, c0;
     blk_origin<M, V>(tid, rd, r0, c0);
     cx<float> q[4], zz[4];
@@ -593,9 +639,12 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
     }
     __syncthreads();
   } else {
-    // the forward transform's first three passes (rows, rows, columns)
-    fft_pass<float, M, V, false, true, false>(A, tws, tid);
-    __syncthreads();
+    // the forward transform's first three passes (rows, rows, columns); with the
+    // direct gather the first one is done
+    if constexpr (!DG) {
+      fft_pass<float, M, V, false, true, false>(A, tws, tid);
+      __syncthreads();
+    }
     if constexpr (AS == 1) load_amps();
     fft_pass<float, M, V, false, false, false>(A, tws, tid);
     __syncthreads();

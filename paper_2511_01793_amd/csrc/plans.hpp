@@ -16,6 +16,11 @@
 // after every pass (m = 64, 8 * 8 split, 1024 threads only).  The plan's other
 // kernels use the LDS passes.  The arithmetic is the same either way, so the
 // results are bitwise those of the other plans with the same split.
+// DG = 1: the patch kernel gathers the exit wave straight into the registers of
+// the first (strided) row pass, item (row, g) of that pass loading its own points,
+// so the pass needs no LDS round trip and no barrier of its own.  The pass's
+// arithmetic is unchanged, so the results are bitwise those of DG = 0.  (Plan
+// (128, 1) with it needs 15 twiddles per thread and spills: measured slower.)
 // AMP is where the patch kernel issues the loads of the measured intensities:
 // 0 with the exit-wave loads at the start, k > 0 after the k-th forward pass.
 // Plans whose registers are tight at 1024 threads issue them late, so the
@@ -30,17 +35,17 @@
 namespace emg {
 
 template <int M, int V> struct Plan;
-template <> struct Plan<32, 0> { static constexpr int R1 = 8, R2 = 4, NT = 256; static constexpr int AMP = 0, XL = 0; };
-template <> struct Plan<32, 1> { static constexpr int R1 = 4, R2 = 8, NT = 256; static constexpr int AMP = 0, XL = 0; };
-template <> struct Plan<64, 0> { static constexpr int R1 = 8, R2 = 8, NT = 1024; static constexpr int AMP = 0, XL = 0; };
-template <> struct Plan<64, 1> { static constexpr int R1 = 16, R2 = 4, NT = 1024; static constexpr int AMP = 2, XL = 0; };
-template <> struct Plan<64, 2> { static constexpr int R1 = 4, R2 = 16, NT = 1024; static constexpr int AMP = 0, XL = 0; };
-template <> struct Plan<64, 3> { static constexpr int R1 = 8, R2 = 8, NT = 1024; static constexpr int AMP = 0, XL = 1; };
-template <> struct Plan<128, 0> { static constexpr int R1 = 16, R2 = 8, NT = 1024; static constexpr int AMP = 3, XL = 0; };
-template <> struct Plan<128, 1> { static constexpr int R1 = 8, R2 = 16, NT = 1024; static constexpr int AMP = 2, XL = 0; };
-template <> struct Plan<128, 2> { static constexpr int R1 = 16, R2 = 8, NT = 512; static constexpr int AMP = 0, XL = 0; };
+template <> struct Plan<32, 0> { static constexpr int R1 = 8, R2 = 4, NT = 256; static constexpr int AMP = 0, XL = 0, DG = 0; };
+template <> struct Plan<32, 1> { static constexpr int R1 = 4, R2 = 8, NT = 256; static constexpr int AMP = 0, XL = 0, DG = 0; };
+template <> struct Plan<64, 0> { static constexpr int R1 = 8, R2 = 8, NT = 1024; static constexpr int AMP = 0, XL = 0, DG = 0; };
+template <> struct Plan<64, 1> { static constexpr int R1 = 16, R2 = 4, NT = 1024; static constexpr int AMP = 2, XL = 0, DG = 0; };
+template <> struct Plan<64, 2> { static constexpr int R1 = 4, R2 = 16, NT = 1024; static constexpr int AMP = 0, XL = 0, DG = 0; };
+template <> struct Plan<64, 3> { static constexpr int R1 = 8, R2 = 8, NT = 1024; static constexpr int AMP = 0, XL = 1, DG = 0; };
+template <> struct Plan<128, 0> { static constexpr int R1 = 16, R2 = 8, NT = 1024; static constexpr int AMP = 3, XL = 0, DG = 1; };
+template <> struct Plan<128, 1> { static constexpr int R1 = 8, R2 = 16, NT = 1024; static constexpr int AMP = 2, XL = 0, DG = 0; };
+template <> struct Plan<128, 2> { static constexpr int R1 = 16, R2 = 8, NT = 512; static constexpr int AMP = 0, XL = 0, DG = 0; };
 // m = 256: the tile exceeds LDS; strips of 16 lines per workgroup (kernels_m256.hip)
-template <> struct Plan<256, 0> { static constexpr int R1 = 16, R2 = 16, NT = 256; static constexpr int AMP = 0, XL = 0; };
+template <> struct Plan<256, 0> { static constexpr int R1 = 16, R2 = 16, NT = 256; static constexpr int AMP = 0, XL = 0, DG = 0; };
 
 template <int M> struct PlanCount;
 template <> struct PlanCount<32> { static constexpr int value = 2; };
