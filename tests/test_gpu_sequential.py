@@ -84,9 +84,11 @@ def test_chain_path_epoch_parity_with_the_oracle():
     rec.close()
 
 
-def test_phase_memory_off_the_zero_bins_changes_nothing():
-    p = small(64, 2)
-    say("case: memory without zero bins")
+@pytest.mark.parametrize("m", [64, 128])
+def test_phase_memory_off_the_zero_bins_changes_nothing(m):
+    # the kernels compiled with the phase memory against those compiled without it
+    p = small(m, 2)
+    say("case: memory without zero bins", m)
     o1, q1, s1 = sweep(p, path="fused")
     o2, q2, s2 = sweep(p, path="fused", zero_phase_memory=True)
     o3, q3, s3 = sweep(p, path="chain", zero_phase_memory=True)
@@ -94,13 +96,14 @@ def test_phase_memory_off_the_zero_bins_changes_nothing():
     assert torch.equal(o1, o3) and torch.equal(q1, q3)
 
 
+@pytest.mark.parametrize("m", [32, 128])
 @pytest.mark.parametrize("path", ["fused", "plain", "chain"])
-def test_phase_memory_on_exact_zero_bins_matches_the_oracle(path):
+def test_phase_memory_on_exact_zero_bins_matches_the_oracle(path, m):
     """First visit of pattern k with a random state (no zero bins: the memory takes its
     phases), second visit with a constant exit wave (every bin but DC exactly zero: the
     revised wave carries the first visit's phases there)."""
-    p = small(32, 1)
-    say("case: phase memory", path)
+    p = small(m, 1)
+    say("case: phase memory", path, m)
     rng = np.random.default_rng(3)
     k = 7
     Qr = (rng.standard_normal((p.m, p.m)) + 1j * rng.standard_normal((p.m, p.m))).astype(np.complex64)
