@@ -381,9 +381,9 @@ __device__ __forceinline__ float project_amp(cx<float>& P, float amp, float2* ph
   }
   return diff * diff;
 }
-// measured amplitude a = sqrt(max(d, 0)) of one intensity (hardware square root,
-// within one ulp)
-__device__ __forceinline__ float amplitude(float d) { return __builtin_amdgcn_sqrtf(fmaxf(d, 0.f)); }
+// measured amplitude a = sqrt(max(d, 0)) of one laid-out intensity (hardware square
+// root, within one ulp): the layout (k_layout) stores max(d, 0), so d >= 0 here
+__device__ __forceinline__ float amplitude(float d) { return __builtin_amdgcn_sqrtf(d); }
 template <int M>
 __device__ __forceinline__ float project_px(cx<float>& P, float dval, float2* ph = nullptr,
                                             bool write = false) {
@@ -1478,7 +1478,7 @@ __global__ __launch_bounds__(256) void k_layout(const float* d, float* dperm, do
   int nonfinite = 0;
   for (int e = tid; e < M * M; e += 256) {
     const float v = src[freq_of_pos<M, V>(e / M) * M + freq_of_pos<M, V>(e % M)];
-    dst[e] = v;
+    dst[e] = fmaxf(v, 0.f);  // amplitude() takes the root of this without a test
     nonfinite |= !isfinite(v);
     acc += (double)v;
   }

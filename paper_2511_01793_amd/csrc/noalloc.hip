@@ -70,7 +70,8 @@ __global__ __launch_bounds__((Plan<M, 0>::NT)) void k_misfit_natural(const float
   const float* dk = d + (size_t)k * M * M;
   const double phi = misfit_pattern<M, 0>(
       obj, nc, probe, pk,
-      [&](int r, int c) { return dk[freq_of_pos<M, 0>(r) * M + freq_of_pos<M, 0>(c)]; }, A, tws,
+      [&](int r, int c) { return fmaxf(dk[freq_of_pos<M, 0>(r) * M + freq_of_pos<M, 0>(c)], 0.f); },
+      A, tws,
       redd, tid);
   if (tid == 0) terms[k] = phi;
 }

@@ -351,3 +351,42 @@ def test_zero_probe_normalisation_rejected():
         rec.normalize_probe(probe)
     assert ei.value.name == "E_DEGENERATE"
     rec.close()
+
+
+@pytest.mark.parametrize("m", [32, 128])
+def test_negative_intensities_give_zero_amplitude(m):
+    """a = sqrt(max(d, 0)): background-subtracted data with negative bins.  The library clamps
+    the intensities once when it lays them out; the oracle clamps in its amplitudes.  Step,
+    sampled misfit and full misfit against the oracle; the allocation-free misfit, which reads
+    the caller's raw intensities, bitwise equal to the context's."""
+    import dataclasses
+    import paper_2511_01793_amd.emagpie as E
+    p = small(m=m, n=3 * m + 4, L=2, B=7)
+    d = p.intensities - np.float32(0.5) * np.float32(p.intensities.mean())
+    assert (d < 0).mean() > 0.2  # a large share of the bins is negative
+    p = dataclasses.replace(p, intensities=np.ascontiguousarray(d, dtype=np.float32))
+    say("case: negative intensities", m)
+    rec = make_rec(p, path="fused")
+    obj, probe = init_state(p, rec)
+    a = amps(p)
+    idx = np.array([3, 0, 12, 7, 21, 9, 16], dtype=np.int32)
+    z0, q0 = host(obj), host(probe)
+    sampled = torch.zeros((), dtype=torch.float64, device="cuda")
+    rec.step(obj, probe, idx, sampled=sampled)
+    torch.cuda.synchronize()
+    q1, z1, info = O.step_minibatch(q0, z0, p.positions, a, idx, alpha=p.alpha, levels=2)
+    assert rel(host(obj), z1) < STEP_TOL and rel(host(probe), q1) < STEP_TOL
+    s = info["sampled_misfit"]
+    assert abs(float(sampled.item()) - s) <= MISFIT_TOL * s
+    phi = rec.misfit(obj, probe)
+    ref = O.misfit(host(probe), host(obj), p.positions, a)
+    assert abs(float(phi.item()) - ref) <= MISFIT_TOL * ref
+    rec.close()
+    dd = torch.from_numpy(p.intensities).cuda()
+    pos = torch.from_numpy(np.ascontiguousarray(p.positions, dtype=np.int32)).cuda()
+    rec0 = make_rec(p, path="fused", fft_plan=0)
+    phi0 = rec0.misfit(obj, probe)
+    phi_na = E.misfit_noalloc(pos, dd, obj, probe)
+    torch.cuda.synchronize()
+    assert float(phi_na.item()) == float(phi0.item())
+    rec0.close()
