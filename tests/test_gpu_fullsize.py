@@ -61,7 +61,8 @@ def c3():
 
 
 # the default plan, and the configuration the autotuner picks for this workload
-@pytest.mark.parametrize("path, plan, shape", [("graph", 0, 0), ("fused", 1, 2), ("fused", 1, 10)])
+@pytest.mark.parametrize("path, plan, shape", [("graph", 0, 0), ("fused", 1, 2), ("fused", 1, 10),
+                                               ("fused", 0, 8)])
 def test_c3_minibatch_step_parity_three_levels(c3, path, plan, shape):
     # 1024^2 object, 128^2 probe, 10000 positions, minibatch 256, three levels; full
     # minibatches from mid-reconstruction states.  At the initial guess (z = 1, smooth

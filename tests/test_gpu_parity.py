@@ -390,3 +390,26 @@ def test_negative_intensities_give_zero_amplitude(m):
     torch.cuda.synchronize()
     assert float(phi_na.item()) == float(phi0.item())
     rec0.close()
+
+
+def test_full_misfit_at_m128_many_patterns():
+    """The full misfit at m = 128 over 900 patterns (several blocks per CU in sequence):
+    against the oracle, and bitwise the allocation-free misfit, which reads the caller's
+    natural-order intensities instead of the laid-out ones."""
+    import paper_2511_01793_amd.emagpie as E
+    p = problem("tiny", n=512, m=128, scan=("raster", 30, 12, 1), photons=1e6, B=64, L=2,
+                alpha=0.05, seed=23)
+    assert p.n_pos >= 2 * 256
+    say("case: misfit, many patterns", p.n_pos)
+    rec = make_rec(p, path="fused", fft_plan=0)
+    obj, probe = init_state(p, rec)
+    rec.epoch(obj, probe, 0)
+    phi = rec.misfit(obj, probe)
+    d = torch.from_numpy(p.intensities).cuda()
+    pos = torch.from_numpy(np.ascontiguousarray(p.positions, dtype=np.int32)).cuda()
+    phi_na = E.misfit_noalloc(pos, d, obj, probe)
+    torch.cuda.synchronize()
+    assert float(phi.item()) == float(phi_na.item())
+    ref = O.misfit(host(probe), host(obj), p.positions, amps(p))
+    assert abs(float(phi.item()) - ref) <= MISFIT_TOL * ref
+    rec.close()
