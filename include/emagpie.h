@@ -108,9 +108,10 @@ typedef struct {
  * the LDS transforms and the threads per patch; the finalize shape fixes the
  * threads per work item, the object tile side and the order the workgroups take
  * the tiles in (fin_order 0: row-major; 1: contiguous bands of tile rows per
- * XCD; 2: tile rows dealt to the XCDs in turn, row r to XCD r mod 8).  Plans that share (r1, r2) give bitwise-identical results; other splits
- * round the same transform differently (and lay the intensities out in their
- * own order).  Finalize shapes never change results.
+ * XCD; 2: tile rows dealt to the XCDs in turn, row r to XCD r mod 8).  Plans
+ * that share (r1, r2) give bitwise-identical results; other splits round the
+ * same transform differently (and lay the intensities out in their own
+ * order).  Finalize shapes never change results.
  */
 typedef struct {
   int32_t fft_plan, r1, r2, threads;
