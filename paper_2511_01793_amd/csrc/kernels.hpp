@@ -6,7 +6,8 @@
 // One workgroup owns one m x m scan patch in the patch stage: it gathers the
 // object window, forms the exit wave psi = Q . z_k (Def. 2.1), runs the
 // forward 2-D DFT (LDS passes; one m = 64 plan keeps each line in registers
-// across lanes instead), projects onto the measured moduli (Def. 2.1,
+// across lanes instead, and one m = 128 plan gathers straight into the registers
+// of its first pass), projects onto the measured moduli (Def. 2.1,
 // theta(0) = 0), runs the inverse DFT, and applies the per-pixel surrogate
 // algebra: the MAGPIE coarse correction (Sec. 3.2, Eqs. 12-15, in its
 // block-ratio form), the object numerator conj(Q) R + u z' (Eq. 7 / Eq. 9 as
