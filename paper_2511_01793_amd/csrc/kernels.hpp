@@ -151,6 +151,24 @@ __device__ __forceinline__ void st_pair(float2* p, size_t i, cx<float> a, cx<flo
   *reinterpret_cast<float4*>(p + i) = make_float4(a.re, a.im, b.re, b.im);
 }
 
+// Stores that write through this XCD's L2 (the agent-scope cache policy).  The
+// per-slot numerators are read back by the finalize, a later kernel spread over every
+// XCD; held dirty in the writer's L2 they would only be written back at the kernel
+// boundary, after the last workgroup, instead of beside the arithmetic.  A raw buffer
+// over one slot's m^2 values (16-byte pairs at byte offsets below 2^31).
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer of dwords (gfx9 resource word 3)
+constexpr int kCachePolicyThrough = 16;   // sc1: coherent at agent scope
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t through_buffer(float2* base, int m2) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, m2 * (int)sizeof(float2), kBufferWord3);
+}
+__device__ __forceinline__ void st_pair_through(__amdgpu_buffer_rsrc_t r, int i, cx<float> a,
+                                                cx<float> b) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  const v4i v = {__float_as_int(a.re), __float_as_int(a.im), __float_as_int(b.re),
+                 __float_as_int(b.im)};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, i * (int)sizeof(float2), 0, kCachePolicyThrough);
+}
+
 
 template <int M, int V>
 struct Px {
@@ -316,8 +334,10 @@ __device__ __forceinline__ void pixel_update_body(const StepArgs& a, int s, int 
       if constexpr (ZP) {
         st_pair(a.zplus, o, N[2 * i], N[2 * i + 1]);
       } else {
-        st_pair(a.numer, o, N[2 * i], N[2 * i + 1]);
-        st_pair(a.pnum, o, Mn[2 * i], Mn[2 * i + 1]);
+        // the slot's numerator buffers, written through the L2
+        const int ob = (r0 + i) * M + c0;  // o - base
+        st_pair_through(through_buffer(a.numer + base, M * M), ob, N[2 * i], N[2 * i + 1]);
+        st_pair_through(through_buffer(a.pnum + base, M * M), ob, Mn[2 * i], Mn[2 * i + 1]);
         if (!slot_den)
           *reinterpret_cast<float2*>(a.pden + o) = make_float2(E[2 * i], E[2 * i + 1]);
         if (s == 0)
