@@ -154,12 +154,18 @@ __device__ __forceinline__ void st_pair(float2* p, size_t i, cx<float> a, cx<flo
 // Stores that write through this XCD's L2 (the agent-scope cache policy).  The
 // per-slot numerators are read back by the finalize, a later kernel spread over every
 // XCD; held dirty in the writer's L2 they would only be written back at the kernel
-// boundary, after the last workgroup, instead of beside the arithmetic.  A raw buffer
-// over one slot's m^2 values (16-byte pairs at byte offsets below 2^31).
+// boundary, after the last workgroup, instead of beside the arithmetic.  The m = 256
+// stages write the per-minibatch stack buffer the same way.  A raw buffer over one
+// slot's values (byte offsets below 2^31).
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer of dwords (gfx9 resource word 3)
 constexpr int kCachePolicyThrough = 16;   // sc1: coherent at agent scope
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t through_buffer(float2* base, int m2) {
   return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, m2 * (int)sizeof(float2), kBufferWord3);
+}
+__device__ __forceinline__ void st_through(__amdgpu_buffer_rsrc_t r, int i, cx<float> a) {
+  typedef int v2i __attribute__((ext_vector_type(2)));
+  const v2i v = {__float_as_int(a.re), __float_as_int(a.im)};
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, i * (int)sizeof(float2), 0, kCachePolicyThrough);
 }
 __device__ __forceinline__ void st_pair_through(__amdgpu_buffer_rsrc_t r, int i, cx<float> a,
                                                 cx<float> b) {

@@ -80,9 +80,11 @@ __global__ __launch_bounds__(256) void k256_rows_fwd(StepArgs a, int k0) {
     a.part_q[s * S + rb] = qm;
     a.part_z[s * S + rb] = zm;
   }
+  // the strip to the stack buffer, written through the L2 (the column blocks read it
+  // in the next kernel)
   float2* out = a.stack + (size_t)s * M * M + (size_t)row0 * M;
 #pragma unroll
-  for (int r = 0; r < S; ++r) st(out, (size_t)r * M + tid, A[r * LSR + tid]);
+  for (int r = 0; r < S; ++r) st_through(through_buffer(out, S * M), r * M + tid, A[r * LSR + tid]);
 }
 
 // 2. column block cb of slot s: forward column passes, then in the pair pass the
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(256) void k256_cols(StepArgs a, int k0) {
 #pragma unroll
     for (int e = 0; e < S; ++e) {
       const int idx = tid + e * NT, row = idx / S, cl = idx % S;
-      st(blk, (size_t)row * M + cl, A[row * LSC + cl]);
+      st_through(through_buffer(blk, M * M), row * M + cl, A[row * LSC + cl]);
     }
   }
 }
