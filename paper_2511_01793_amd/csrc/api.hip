@@ -90,6 +90,24 @@ void xcd_listing_sweep(int4* d, int n, int B, int xcc, std::vector<int4>& tmp) {
   for (int s0 = 0; s0 < n; s0 += B) xcd_listing(d + s0, std::min(B, n - s0), xcc, tmp);
 }
 
+// Launch order of the full misfit: every pattern once, sorted by window corner and
+// dealt to the XCDs like a minibatch listing (the x-th contiguous part of the sorted
+// run to blocks x, x + X, ...), so the windows one XCD transforms lie in one band of
+// the object and are re-read from its L2.  When X does not divide n, the last n mod X
+// sorted patterns follow at the end.  The terms are stored by pattern index, so the
+// order changes no result.
+void misfit_order(const int32_t* pos, int n, int xcc, std::vector<int4>& out) {
+  std::vector<int4> t(n);
+  for (int k = 0; k < n; ++k) t[k] = make_int4(k, pos[2 * k], pos[2 * k + 1], 0);
+  std::stable_sort(t.begin(), t.end(), [](const int4& p, const int4& q) {
+    return p.y != q.y ? p.y < q.y : p.z < q.z;
+  });
+  out.resize(n);
+  const int X = std::max(1, xcc), per = n / X, head = per * X;
+  for (int i = 0; i < head; ++i) out[i] = t[(i % X) * per + i / X];
+  for (int i = head; i < n; ++i) out[i] = t[i];
+}
+
 struct Region {
   size_t off, bytes;
 };
@@ -101,8 +119,8 @@ bool wants_tuning(const emagpie_config& c) {
 }
 
 struct Layout {
-  Region dperm, pos, slots, tw32, tw64, numer, pnum, pden, pden_slot, phi, stack, zmax, ubuf, Dbuf, scal,
-      bar, phi_all, gz, gq, tune_obj, tune_probe, phase, part;
+  Region dperm, pos, slots, morder, tw32, tw64, numer, pnum, pden, pden_slot, phi, stack, zmax, ubuf, Dbuf,
+      scal, bar, phi_all, gz, gq, tune_obj, tune_probe, phase, part;
   int grad_chunk;
   size_t total;
 };
@@ -121,6 +139,7 @@ Layout make_layout(const emagpie_config& c) {
   L.dperm = take(N * m2 * 4);
   L.pos = take(N * 8);
   L.slots = take(std::max(N, B) * 16);
+  L.morder = take(c.m == 256 ? 0 : N * 16);
   L.tw32 = take((size_t)c.m * 8);
   L.tw64 = take((size_t)c.m * 16);
   L.numer = take(B * m2 * 8);
@@ -199,6 +218,7 @@ struct emagpie_ctx_s {
   float* dperm;
   int2* pos;
   int4* slots;  // per slot of the current sweep / batch: (k, row, col, 0)
+  int4* morder;  // every pattern, in the full misfit's launch order (m < 256)
   float2* tw32;
   double2* tw64;
   float2 *numer, *pnum, *stack;
@@ -700,6 +720,7 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
   ctx->dperm = reinterpret_cast<float*>(w + lay.dperm.off);
   ctx->pos = reinterpret_cast<int2*>(w + lay.pos.off);
   ctx->slots = reinterpret_cast<int4*>(w + lay.slots.off);
+  ctx->morder = reinterpret_cast<int4*>(w + lay.morder.off);
   ctx->tw32 = reinterpret_cast<float2*>(w + lay.tw32.off);
   ctx->tw64 = reinterpret_cast<double2*>(w + lay.tw64.off);
   ctx->numer = reinterpret_cast<float2*>(w + lay.numer.off);
@@ -762,6 +783,13 @@ emagpie_status emagpie_init(emagpie_ctx* out, const emagpie_config* cfg,
     return hipfail(e, "upload twiddles");
   if ((e = hipMemcpyAsync(ctx->pos, p2.data(), c.n_pos * sizeof(int2), hipMemcpyHostToDevice, s)) != hipSuccess)
     return hipfail(e, "upload positions");
+  std::vector<int4> order;
+  if (c.m != 256) {
+    misfit_order(positions_host, c.n_pos, ctx->num_xcc, order);
+    if ((e = hipMemcpyAsync(ctx->morder, order.data(), c.n_pos * sizeof(int4), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+      return hipfail(e, "upload misfit order");
+  }
   if ((e = hipMemsetAsync(ctx->scal_i, 0, 64, s)) != hipSuccess) return hipfail(e, "clear flags");
   if (ctx->phase &&
       (e = emg::launch_fill_c64(ctx->phase, (size_t)c.n_pos * c.m * c.m, make_float2(1.f, 0.f), s)) !=
@@ -1097,7 +1125,7 @@ emagpie_status emagpie_check_step(emagpie_ctx ctx, void* obj_dev, void* probe_de
   EMG_HIP(emg::launch_sum_doubles(ctx->phi, b, out3_dev + 1, s));
   EMG_HIP(emg::launch_misfit_terms(m, v, static_cast<const float2*>(obj_dev), ctx->cfg.n_cols,
                                    static_cast<const float2*>(probe_dev), ctx->dperm, ctx->pos,
-                                   ctx->slots, b, ctx->tw32, ctx->phi, s));
+                                   ctx->slots, b, ctx->tw32, ctx->phi, 0, s));
   EMG_HIP(emg::launch_sum_doubles(ctx->phi, b, out3_dev + 2, s));
   return EMAGPIE_OK;
 }
@@ -1118,9 +1146,11 @@ emagpie_status emagpie_misfit(emagpie_ctx ctx, const void* obj_dev, const void* 
     EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
     return EMAGPIE_OK;
   }
+  // the patterns in the context's XCD order, each term at its pattern's index, so the
+  // sum runs in pattern order whatever the device
   EMG_HIP(emg::launch_misfit_terms(ctx->cfg.m, ctx->cfg.fft_plan, static_cast<const float2*>(obj_dev),
                                    ctx->cfg.n_cols, static_cast<const float2*>(probe_dev), ctx->dperm,
-                                   ctx->pos, nullptr, ctx->cfg.n_pos, ctx->tw32, ctx->phi_all, s));
+                                   ctx->pos, ctx->morder, ctx->cfg.n_pos, ctx->tw32, ctx->phi_all, 1, s));
   EMG_HIP(emg::launch_sum_doubles(ctx->phi_all, ctx->cfg.n_pos, misfit_dev, s));
   return EMAGPIE_OK;
 }

@@ -1275,12 +1275,14 @@ template <int M, int V>
 __global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, int n,
                                                         const float2* probe, const float* dperm,
                                                         const int2* pos, const int4* slot,
-                                                        const float2* tw, double* phi_all) {
+                                                        const float2* tw, double* phi_all,
+                                                        int by_pattern) {
   __shared__ cx<float> A[M * lds_stride<M>()];
   __shared__ cx<float> tws[M];
   __shared__ double redd[16];
   constexpr int NT = Px<M, V>::NT;
-  // all patterns (slot == nullptr: block k is pattern k) or the patterns of a slot list
+  // all patterns (slot == nullptr: block k is pattern k) or the patterns of a slot list;
+  // the term goes to the block's place, or with by_pattern to its pattern's index
   const int tid = threadIdx.x;
   const int k = slot ? slot[blockIdx.x].x : (int)blockIdx.x;
   const int2 pk = slot ? make_int2(slot[blockIdx.x].y, slot[blockIdx.x].z) : pos[k];
@@ -1289,7 +1291,7 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, 
   const double phi = misfit_pattern<M, V>(obj, n, probe, pk,
                                           [&](int r, int c) { return dk[r * M + c]; }, A, tws,
                                           redd, tid);
-  if (tid == 0) phi_all[blockIdx.x] = phi;
+  if (tid == 0) phi_all[by_pattern ? k : (int)blockIdx.x] = phi;
 }
 
 // Quadratic surrogate of Eq. 3 for the slots of a batch: 1/2 ||Q . z_k - R_k||^2 with the
@@ -1755,11 +1757,11 @@ hipError_t Launchers<M>::normalize(float2* probe, double dp_avg, int* flag, hipS
 template <int M>
 hipError_t Launchers<M>::misfit(int v, const float2* obj, int n, const float2* probe,
                                 const float* dperm, const int2* pos, const int4* slot, int count,
-                                const float2* tw, double* phi_out, hipStream_t s) {
+                                const float2* tw, double* phi_out, int by_pattern, hipStream_t s) {
   return with_plan<M>(v, [&](auto vc) {
     constexpr int V = decltype(vc)::value;
     hipLaunchKernelGGL((k_misfit<M, V>), dim3(count), dim3(Plan<M, V>::NT), 0, s, obj, n, probe,
-                       dperm, pos, slot, tw, phi_out);
+                       dperm, pos, slot, tw, phi_out, by_pattern);
     return hipGetLastError();
   });
 }

@@ -125,8 +125,8 @@ hipError_t launch_normalize_probe(int m, float2* probe, double dp_avg, int* zero
 }
 hipError_t launch_misfit_terms(int m, int v, const float2* obj, int n, const float2* probe,
                                const float* dperm, const int2* pos, const int4* slot, int count,
-                               const float2* tw, double* phi_out, hipStream_t s) {
-  EMG_BY_M(m, misfit(v, obj, n, probe, dperm, pos, slot, count, tw, phi_out, s));
+                               const float2* tw, double* phi_out, int by_pattern, hipStream_t s) {
+  EMG_BY_M(m, misfit(v, obj, n, probe, dperm, pos, slot, count, tw, phi_out, by_pattern, s));
 }
 hipError_t launch_revised_waves(int m, int v, const StepArgs& a, hipStream_t s) {
   EMG_BY_M(m, revised_waves(v, a, s));

@@ -424,7 +424,7 @@ hipError_t Launchers256::persistent_epoch(int, int, const StepArgs&, int, int, i
   return hipErrorInvalidValue;
 }
 hipError_t Launchers256::misfit(int, const float2*, int, const float2*, const float*, const int2*,
-                                const int4*, int, const float2*, double*, hipStream_t) {
+                                const int4*, int, const float2*, double*, int, hipStream_t) {
   return hipErrorInvalidValue;
 }
 hipError_t Launchers256::revised_waves(int, const StepArgs&, hipStream_t) { return hipErrorInvalidValue; }

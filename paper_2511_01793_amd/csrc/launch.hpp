@@ -103,10 +103,11 @@ hipError_t launch_normalize_probe(int m, float2* probe, double dp_avg, int* zero
 hipError_t launch_chain_sweep(int m, int v, int L, const StepArgs& a, int n_steps, hipStream_t s);
 
 // misfit terms, unreduced: of all patterns (slot == nullptr; count = N, pattern k at
-// pos[k]) or of the count patterns of a slot list -> phi_out (count doubles)
+// pos[k]) or of the count patterns of a slot list -> phi_out (count doubles): term j of
+// the list at phi_out[j], or at phi_out[k] (its pattern's index) when by_pattern is set
 hipError_t launch_misfit_terms(int m, int v, const float2* obj, int n, const float2* probe,
                                const float* dperm, const int2* pos, const int4* slot, int count,
-                               const float2* tw, double* phi_out, hipStream_t s);
+                               const float2* tw, double* phi_out, int by_pattern, hipStream_t s);
 
 // Check mode of one minibatch, in three parts on a.slot / a.b:
 //   revised waves R_k of the current state into a.stack and Phi_k into a.phi (the plain
@@ -177,7 +178,7 @@ struct Launchers {
   static hipError_t normalize(float2* probe, double dp_avg, int* flag, hipStream_t s);
   static hipError_t misfit(int v, const float2* obj, int n, const float2* probe, const float* dperm,
                            const int2* pos, const int4* slot, int count, const float2* tw,
-                           double* phi_out, hipStream_t s);
+                           double* phi_out, int by_pattern, hipStream_t s);
   static hipError_t revised_waves(int v, const StepArgs& a, hipStream_t s);
   static hipError_t numerators(int v, int L, const StepArgs& a, hipStream_t s);
   static hipError_t surrogate(int v, const StepArgs& a, double* terms, hipStream_t s);
@@ -208,7 +209,7 @@ struct Launchers256 {
   static hipError_t normalize(float2* probe, double dp_avg, int* flag, hipStream_t s);
   static hipError_t misfit(int v, const float2* obj, int n, const float2* probe, const float* dperm,
                            const int2* pos, const int4* slot, int count, const float2* tw,
-                           double* phi_out, hipStream_t s);
+                           double* phi_out, int by_pattern, hipStream_t s);
   static hipError_t revised_waves(int v, const StepArgs& a, hipStream_t s);
   static hipError_t numerators(int v, int L, const StepArgs& a, hipStream_t s);
   static hipError_t surrogate(int v, const StepArgs& a, double* terms, hipStream_t s);
