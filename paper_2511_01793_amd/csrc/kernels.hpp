@@ -1294,6 +1294,140 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, 
   if (tid == 0) phi_all[by_pattern ? k : (int)blockIdx.x] = phi;
 }
 
+// The misfit term of one pattern for the 16 x 8 split at m = 128 (plans 0 and 2)
+// with two workgroups per CU: 512 threads, and half the transformed tile in LDS at a
+// time (S: 128 rows of 64, row stride 65), the other half held in registers.  The
+// rows go in two chunks of 64: the strided row pass loads its exit wave straight
+// from memory (item (row, g) its points g + 16 j), the contiguous row pass leaves
+// each thread one 16-point run per chunk, one in columns 0..63 and one in 64..127
+// (the second chunk's item has the first one's group with bit 2 flipped).  Then
+// the column passes of columns 0..63 in LDS, and those of 64..127 once the other
+// runs are written in.  Every DFT, twiddle product and misfit term is the one the
+// plan's LDS passes compute (misfit_pattern), so the terms are bitwise the same;
+// only the order of the pattern's FP64 sum differs.  The caller has staged the
+// twiddles in tws and synchronised; INT as in misfit_pattern.
+template <int M, int V>
+struct HalfMisfit {
+  static constexpr bool value = M == 128 && Plan<M, V>::R1 == 16 && Plan<M, V>::R2 == 8;
+  static constexpr int NT = 512, H = M / 2;
+  static constexpr int LR = M + 1;  // row chunk: 64 rows of 128, stride 129
+  static constexpr int LC = H + 1;  // column half: 128 rows of 64, stride 65
+  static constexpr int LDS = M * LC;
+  static_assert(H * LR <= M * LC, "row chunk fits the column-half buffer");
+};
+
+template <int M, int V, class INT>
+__device__ __forceinline__ double misfit_pattern_half(const float2* obj, int n, const float2* probe,
+                                                      int2 pk, INT intensity, cx<float>* S,
+                                                      const cx<float>* tws, double* redd, int tid) {
+  using HM = HalfMisfit<M, V>;
+  constexpr int NTH = HM::NT, H = HM::H, LR = HM::LR, LC = HM::LC;
+  constexpr int R1 = Plan<M, V>::R1, R2 = Plan<M, V>::R2;
+  static_assert(HM::value, "16 x 8 split at m = 128");
+  const int rl = tid % H, gq = tid / H;  // contiguous row item: row rl of the chunk, group gq
+  cx<float> hold[2][R1];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    // strided row pass: 64 rows x 16 groups, two items per thread
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int w = tid + it * NTH;
+      const int r = w / R1, g = w % R1;
+      const int row = h * H + r;
+      cx<float> v[R2];
+#pragma unroll
+      for (int j = 0; j < R2; ++j) {
+        const int c = g + R1 * j;
+        v[j] = mul(ld(probe, (size_t)row * M + c), ld(obj, (size_t)(pk.x + row) * n + pk.y + c));
+      }
+      dft_small<float, false, R2, M>(v, tws);
+#pragma unroll
+      for (int j = 1; j < R2; ++j) v[j] = mul_fma(tws[g * j], v[j]);
+#pragma unroll
+      for (int j = 0; j < R2; ++j) S[r * LR + g + R1 * j] = v[j];
+    }
+    __syncthreads();
+    // contiguous row pass: row rl, group gq (chunk 0) or gq ^ 4 (chunk 1)
+    const int g = gq ^ (h * (R2 / 2));
+#pragma unroll
+    for (int j = 0; j < R1; ++j) hold[h][j] = S[rl * LR + R1 * g + j];
+    dft_small<float, false, R1, M>(hold[h], nullptr);
+    __syncthreads();
+  }
+  // the run in columns 0..63 (A) and the one in 64..127 (B)
+  const bool first = gq < R2 / 2;
+  const int rowA = first ? rl : H + rl, rowB = first ? H + rl : rl;
+  const int cA = R1 * (gq & (R2 / 2 - 1));  // column of the run within its half
+  cx<float> hB[R1];
+  double acc = 0.0;
+  const int line = tid % H, gl = tid / H;  // contiguous column item: column line, group gl
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    if (half == 0) {
+#pragma unroll
+      for (int j = 0; j < R1; ++j) {
+        S[rowA * LC + cA + j] = first ? hold[0][j] : hold[1][j];
+        hB[j] = first ? hold[1][j] : hold[0][j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < R1; ++j) S[rowB * LC + cA + j] = hB[j];
+    }
+    // this half's intensities, in the order the last pass visits them
+    float dv[R1];
+#pragma unroll
+    for (int j = 0; j < R1; ++j) dv[j] = intensity(R1 * gl + j, half * H + line);
+    __syncthreads();
+    // strided column pass over the half's 64 columns, two items per thread
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int w = tid + it * NTH;
+      const int ln = w % H, g = w / H;
+      cx<float> v[R2];
+#pragma unroll
+      for (int j = 0; j < R2; ++j) v[j] = S[(g + R1 * j) * LC + ln];
+      dft_small<float, false, R2, M>(v, tws);
+#pragma unroll
+      for (int j = 1; j < R2; ++j) v[j] = mul_fma(tws[g * j], v[j]);
+#pragma unroll
+      for (int j = 0; j < R2; ++j) S[(g + R1 * j) * LC + ln] = v[j];
+    }
+    __syncthreads();
+    // contiguous column pass with the misfit terms
+    cx<float> v[R1];
+#pragma unroll
+    for (int j = 0; j < R1; ++j) v[j] = S[(R1 * gl + j) * LC + line];
+    dft_small<float, false, R1, M>(v, nullptr);
+#pragma unroll
+    for (int j = 0; j < R1; ++j) acc += (double)project_px<M>(v[j], dv[j]);
+    __syncthreads();
+  }
+  const double tot = block_sum<NTH>(acc, redd, tid);
+  return tot / (2.0 * M * M);
+}
+
+template <int M, int V>
+__global__ __launch_bounds__(512, 2) void k_misfit_half(const float2* obj, int n,
+                                                        const float2* probe, const float* dperm,
+                                                        const int2* pos, const int4* slot,
+                                                        const float2* tw, double* phi_all,
+                                                        int by_pattern) {
+  using HM = HalfMisfit<M, V>;
+  __shared__ cx<float> S[HM::LDS];
+  __shared__ cx<float> tws[M];
+  __shared__ double redd[16];
+  const int tid = threadIdx.x;
+  const int k = slot ? slot[blockIdx.x].x : (int)blockIdx.x;
+  const int2 pk = slot ? make_int2(slot[blockIdx.x].y, slot[blockIdx.x].z) : pos[k];
+  const float* dk = dperm + (size_t)k * M * M;
+  stage_twiddles<M, HM::NT>(tw, tws, tid);
+  __syncthreads();
+  const double phi = misfit_pattern_half<M, V>(obj, n, probe, pk,
+                                               [&](int r, int c) { return dk[r * M + c]; }, S, tws,
+                                               redd, tid);
+  if (tid == 0) phi_all[by_pattern ? k : (int)blockIdx.x] = phi;
+}
+
 // Quadratic surrogate of Eq. 3 for the slots of a batch: 1/2 ||Q . z_k - R_k||^2 with the
 // current state (Q, z) and revised exit waves R_k held in a.stack (frozen at an earlier
 // iterate).  FP32 differences, FP64 sum of their squared magnitudes.
@@ -1760,8 +1894,13 @@ hipError_t Launchers<M>::misfit(int v, const float2* obj, int n, const float2* p
                                 const float2* tw, double* phi_out, int by_pattern, hipStream_t s) {
   return with_plan<M>(v, [&](auto vc) {
     constexpr int V = decltype(vc)::value;
-    hipLaunchKernelGGL((k_misfit<M, V>), dim3(count), dim3(Plan<M, V>::NT), 0, s, obj, n, probe,
-                       dperm, pos, slot, tw, phi_out, by_pattern);
+    if constexpr (HalfMisfit<M, V>::value)
+      hipLaunchKernelGGL((k_misfit_half<M, V>), dim3(count), dim3(HalfMisfit<M, V>::NT), 0, s, obj, n,
+                         probe, dperm,
+                         pos, slot, tw, phi_out, by_pattern);
+    else
+      hipLaunchKernelGGL((k_misfit<M, V>), dim3(count), dim3(Plan<M, V>::NT), 0, s, obj, n, probe,
+                         dperm, pos, slot, tw, phi_out, by_pattern);
     return hipGetLastError();
   });
 }

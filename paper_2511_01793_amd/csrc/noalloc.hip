@@ -76,6 +76,29 @@ __global__ __launch_bounds__((Plan<M, 0>::NT)) void k_misfit_natural(const float
   if (tid == 0) terms[k] = phi;
 }
 
+// m = 128: the two-workgroups-per-CU form of the context's misfit kernel (same
+// arithmetic and order of sums, so the two entry points agree bitwise)
+template <int M>
+__global__ __launch_bounds__(512, 2) void k_misfit_natural_half(const float2* obj, int nr, int nc,
+                                                               const float2* probe, const float* d,
+                                                               const int2* pos, Twiddles<M> tw,
+                                                               double* terms) {
+  using HM = HalfMisfit<M, 0>;
+  __shared__ cx<float> S[HM::LDS];
+  __shared__ cx<float> tws[M];
+  __shared__ double redd[16];
+  const int tid = threadIdx.x, k = blockIdx.x;
+  for (int j = tid; j < M; j += HM::NT) tws[j] = cx<float>{tw.w[j].x, tw.w[j].y};
+  __syncthreads();
+  const int2 pk = clamp_window(pos[k], nr, nc, M);
+  const float* dk = d + (size_t)k * M * M;
+  const double phi = misfit_pattern_half<M, 0>(
+      obj, nc, probe, pk,
+      [&](int r, int c) { return fmaxf(dk[freq_of_pos<M, 0>(r) * M + freq_of_pos<M, 0>(c)], 0.f); },
+      S, tws, redd, tid);
+  if (tid == 0) terms[k] = phi;
+}
+
 template <int M>
 hipError_t launch(const float2* obj, int nr, int nc, const float2* probe, const float* d,
                   const int2* pos, int count, double* terms, hipStream_t s) {
@@ -84,8 +107,12 @@ hipError_t launch(const float2* obj, int nr, int nc, const float2* probe, const 
     const double ang = -2.0 * M_PI * (double)j / (double)M;
     tw.w[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
   }
-  hipLaunchKernelGGL((k_misfit_natural<M>), dim3(count), dim3(Plan<M, 0>::NT), 0, s, obj, nr, nc,
-                     probe, d, pos, tw, terms);
+  if constexpr (HalfMisfit<M, 0>::value)
+    hipLaunchKernelGGL((k_misfit_natural_half<M>), dim3(count), dim3(HalfMisfit<M, 0>::NT), 0, s, obj,
+                       nr, nc, probe, d, pos, tw, terms);
+  else
+    hipLaunchKernelGGL((k_misfit_natural<M>), dim3(count), dim3(Plan<M, 0>::NT), 0, s, obj, nr, nc,
+                       probe, d, pos, tw, terms);
   return hipGetLastError();
 }
 
