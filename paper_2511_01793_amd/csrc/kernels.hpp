@@ -1537,16 +1537,15 @@ __device__ __forceinline__ void settle2(int2& v) {
   asm volatile("" : "+v"(v.x), "+v"(v.y));
 }
 
-// object gradient: tile of kGradTile^2 pixels, kGradZGroups x 256 threads
+// object gradient: tile `tile` of kGradTile^2 pixels, kGradZGroups x 256 threads
 template <typename T, int M>
-__global__ __launch_bounds__(256 * kGradZGroups) void k_grad_scatter(GradArgs g, int k0, int cnt,
-                                                                      int first) {
+__device__ __forceinline__ void grad_scatter_tile(const GradArgs& g, int k0, int cnt, int first,
+                                                  int tile, cx<T>* part, int tid) {
   constexpr int TS = kGradTile, GS = kGradZGroups, U = 8;
   static_assert(TS * TS == 256, "one pixel per thread of a group");
-  __shared__ cx<T> part[(GS - 1) * TS * TS];
-  const int tid = threadIdx.x, gi = tid >> 8, q = tid & 255, lane = tid & 63, n = g.n, nr = g.nr;
+  const int gi = tid >> 8, q = tid & 255, lane = tid & 63, n = g.n, nr = g.nr;
   const int tpr = (n + TS - 1) / TS;
-  const int ty = (blockIdx.x / tpr) * TS, tx = (blockIdx.x % tpr) * TS;
+  const int ty = (tile / tpr) * TS, tx = (tile % tpr) * TS;
   const int y = ty + q / TS, x = tx + q % TS;
   const int per = (cnt + GS - 1) / GS, lo = min(cnt, gi * per), hi = min(cnt, lo + per);
   cx<T> acc{T(0), T(0)};
@@ -1596,13 +1595,15 @@ __global__ __launch_bounds__(256 * kGradZGroups) void k_grad_scatter(GradArgs g,
   }
 }
 
-// probe gradient: 256 / kGradQGroups pixels x kGradQGroups pattern groups per block
+// probe gradient: unit `unit` of 256 threads, 256 / kGradQGroups pixels x kGradQGroups
+// pattern groups (part: the unit's 256 partial sums; every thread of the block calls
+// this once, for the barrier)
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_grad_probe(GradArgs g, int cnt, int first) {
+__device__ __forceinline__ void grad_probe_unit(const GradArgs& g, int cnt, int first, int unit,
+                                                cx<T>* part, int tid) {
   constexpr int G = kGradQGroups, PPU = 256 / G, U = 8;
-  __shared__ cx<T> part[256];
-  const int tid = threadIdx.x, gi = tid / PPU, lp = tid % PPU;
-  const int r = blockIdx.x * PPU + lp;
+  const int gi = tid / PPU, lp = tid % PPU;
+  const int r = unit * PPU + lp;
   const bool live = r < M * M;
   const int per = (cnt + G - 1) / G, lo = min(cnt, gi * per), hi = min(cnt, lo + per);
   cx<T> acc{T(0), T(0)};
@@ -1625,6 +1626,29 @@ __global__ __launch_bounds__(256) void k_grad_probe(GradArgs g, int cnt, int fir
     for (int k = 1; k < G; ++k) t = add(t, part[lp + k * PPU]);
     stT<T>(g.gprobe, r, first ? t : add(ldT<T>(g.gprobe, r), t));
   }
+}
+
+// the object and probe reductions of one chunk in one launch: blocks [0, tiles) take
+// object tiles, the others four probe units each (256 threads per unit)
+constexpr int kGradUnitsPerBlock = kGradZGroups;
+inline int grad_tiles(const GradArgs& g) {
+  return ((g.nr + kGradTile - 1) / kGradTile) * ((g.n + kGradTile - 1) / kGradTile);
+}
+inline int grad_probe_blocks(int m) {
+  const int units = (m * m + 256 / kGradQGroups - 1) / (256 / kGradQGroups);
+  return (units + kGradUnitsPerBlock - 1) / kGradUnitsPerBlock;
+}
+template <typename T, int M>
+__global__ __launch_bounds__(256 * kGradZGroups) void k_grad_reduce(GradArgs g, int k0, int cnt,
+                                                                     int first, int tiles) {
+  __shared__ cx<T> part[256 * kGradZGroups];
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x < tiles)
+    grad_scatter_tile<T, M>(g, k0, cnt, first, blockIdx.x, part, tid);
+  else
+    grad_probe_unit<T, M>(g, cnt, first,
+                          ((int)blockIdx.x - tiles) * kGradUnitsPerBlock + (tid >> 8),
+                          part + (tid & ~255), tid & 255);
 }
 
 // ---------------------------------------------------------------------------
@@ -1954,16 +1978,14 @@ hipError_t Launchers<M>::chain(int v, int L, const StepArgs& a, int n_steps, hip
 
 template <typename T, int M, int V>
 static hipError_t grad_t(const GradArgs& g, hipStream_t s) {
-  constexpr int NT = Plan<M, V>::NT, TS = kGradTile, PPU = 256 / kGradQGroups;
-  const int tiles = ((g.nr + TS - 1) / TS) * ((g.n + TS - 1) / TS);
+  constexpr int NT = Plan<M, V>::NT;
+  const int tiles = grad_tiles(g), blocks = tiles + grad_probe_blocks(M);
   for (int k0 = 0; k0 < g.n_pos; k0 += g.chunk) {
     const int cnt = min(g.chunk, g.n_pos - k0);
     const int first = k0 == 0;
     hipLaunchKernelGGL((k_grad_patch<T, M, V>), dim3(cnt), dim3(NT), 0, s, g, k0);
-    hipLaunchKernelGGL((k_grad_scatter<T, M>), dim3(tiles), dim3(256 * kGradZGroups), 0, s, g,
-                       k0, cnt, first);
-    hipLaunchKernelGGL((k_grad_probe<T, M>), dim3((M * M + PPU - 1) / PPU), dim3(256), 0, s, g,
-                       cnt, first);
+    hipLaunchKernelGGL((k_grad_reduce<T, M>), dim3(blocks), dim3(256 * kGradZGroups), 0, s, g, k0,
+                       cnt, first, tiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

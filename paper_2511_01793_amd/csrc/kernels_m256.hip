@@ -220,8 +220,7 @@ __global__ __launch_bounds__(256) void k256_phi_reduce(const double* part_phi, i
 
 // gradient: inverse row passes of strip rb of pattern k0 + s turn the Fourier residual
 // into e_k = Q z_k - R_k; the strip's slot terms conj(Q) e_k (object) and conj(z_k) e_k
-// (probe) go to the gradient slots, for the shared reductions k_grad_scatter and
-// k_grad_probe
+// (probe) go to the gradient slots, for the shared reductions of k_grad_reduce
 __global__ __launch_bounds__(256) void k256_rows_grad(StepArgs a, int k0, float2* gz, float2* gq) {
   using namespace big;
   __shared__ cx<float> A[S * LSR];
@@ -307,11 +306,11 @@ hipError_t Launchers256::misfit_strips(const StepArgs& a, int k0, int count, dou
 }
 
 hipError_t launch_grad256(const StepArgs& a, const GradArgs& g, hipStream_t s) {
-  constexpr int M = 256, TS = kGradTile, PPU = 256 / kGradQGroups;
+  constexpr int M = 256;
   if (!a.part_q || g.chunk < 1) return hipErrorInvalidValue;
   StepArgs x = a;
   x.slot = nullptr;
-  const int tiles = ((g.nr + TS - 1) / TS) * ((g.n + TS - 1) / TS);
+  const int tiles = grad_tiles(g), blocks = tiles + grad_probe_blocks(M);
   for (int k0 = 0; k0 < g.n_pos; k0 += g.chunk) {
     const int cnt = min(g.chunk, g.n_pos - k0);
     const dim3 grid(cnt * big::S), block(big::NT);
@@ -322,10 +321,8 @@ hipError_t launch_grad256(const StepArgs& a, const GradArgs& g, hipStream_t s) {
     hipLaunchKernelGGL(k256_phi_reduce, dim3((cnt + 255) / 256), dim3(256), 0, s,
                        (const double*)x.part_phi, cnt, g.phi_all + k0, 1.0 / (2.0 * M * M));
     const int first = k0 == 0;
-    hipLaunchKernelGGL((k_grad_scatter<float, M>), dim3(tiles), dim3(256 * kGradZGroups), 0, s, g,
-                       k0, cnt, first);
-    hipLaunchKernelGGL((k_grad_probe<float, M>), dim3((M * M + PPU - 1) / PPU), dim3(256), 0, s, g,
-                       cnt, first);
+    hipLaunchKernelGGL((k_grad_reduce<float, M>), dim3(blocks), dim3(256 * kGradZGroups), 0, s, g,
+                       k0, cnt, first, tiles);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
