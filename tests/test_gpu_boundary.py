@@ -94,6 +94,35 @@ def test_rectangular_object_gradient():
     rec.close()
 
 
+
+@pytest.mark.parametrize("plan", [0, 1])
+def test_rectangular_object_misfit_at_m128(plan):
+    """m = 128 on a rectangular object: plan 0 (16 x 8 split) runs the two-workgroups-per-CU
+    misfit kernel, plan 1 the one-tile-per-workgroup kernel; both against the oracle, and the
+    allocation-free misfit bitwise equal to the plan-0 context."""
+    import paper_2511_01793_amd.emagpie as E
+    p = rect_problem(200, 330, m=128, step=(24, 29), photons=1e6, seed=7)
+    a = O.amplitudes(p["intensities"])
+    say("case: rectangular misfit m=128", plan, len(p["positions"]))
+    rec, obj, probe = rect_rec(p, minibatch=8, levels=3, fft_plan=plan)
+    rec.epoch(obj, probe, 0)
+    phi = float(rec.misfit(obj, probe).item())
+    torch.cuda.synchronize()
+    ref = O.misfit(host(probe), host(obj), p["positions"], a)
+    assert abs(phi - ref) <= MISFIT_TOL * ref
+    if plan == 0:
+        pos = torch.from_numpy(np.ascontiguousarray(p["positions"])).cuda()
+        d = torch.from_numpy(p["intensities"]).cuda()
+        out = torch.full((), -1.0, dtype=torch.float64, device="cuda")
+        st = E.lib().emagpie_misfit_noalloc(200, 330, 128, len(p["positions"]), pos.data_ptr(),
+                                            d.data_ptr(), obj.data_ptr(), probe.data_ptr(),
+                                            out.data_ptr(), E._stream())
+        assert st == 0, E.last_error()
+        torch.cuda.synchronize()
+        assert float(out.item()) == phi
+    rec.close()
+
+
 # ------------------------------------------------------------------ device-side errors
 
 def test_persistent_barrier_timeout_is_reported_by_the_next_call():
