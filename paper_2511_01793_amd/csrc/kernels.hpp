@@ -1406,6 +1406,9 @@ __device__ __forceinline__ double misfit_pattern_half(const float2* obj, int n, 
   return tot / (2.0 * M * M);
 }
 
+// Two workgroups per CU need at most 128 VGPRs (four waves per SIMD): the kernel takes 124
+// as built.  Asking the compiler for four waves per SIMD outright makes it use all 128 and
+// spill, so the bound only states the thread count and a floor of two waves.
 template <int M, int V>
 __global__ __launch_bounds__(512, 2) void k_misfit_half(const float2* obj, int n,
                                                         const float2* probe, const float* dperm,
