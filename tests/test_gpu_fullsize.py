@@ -87,3 +87,19 @@ def test_c3_minibatch_step_parity_three_levels(c3, path, plan, shape):
         assert rel(host(probe), q1) < STEP_TOL, rel(host(probe), q1)
         rec.epoch(obj, probe, 1 + stage)
     rec.close()
+
+
+# the full misfit over all 10000 patterns: plans 0 and 2 (16 x 8 split) run the
+# two-workgroups-per-CU kernel in the XCD order, plan 1 (8 x 16) the one-tile kernel
+@pytest.mark.parametrize("plan", [0, 1, 2])
+def test_c3_full_misfit_parity(c3, plan):
+    p = c3
+    print("case: c3 full misfit", plan, flush=True)
+    rec = make_rec(p, path="fused", seed=p.seed, fft_plan=plan, finalize_shape=8)
+    obj, probe = init_state(p, rec)
+    rec.epoch(obj, probe, 0)
+    phi = float(rec.misfit(obj, probe).item())
+    torch.cuda.synchronize()
+    ref = O.misfit(host(probe), host(obj), p.positions, amps(p))
+    assert abs(phi - ref) <= MISFIT_TOL * ref, (phi, ref)
+    rec.close()
