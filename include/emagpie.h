@@ -53,7 +53,7 @@ typedef enum {
   EMAGPIE_E_DEGENERATE = -5,  /* zero probe (normalisation impossible)         */
   EMAGPIE_E_WORKSPACE = -6,   /* workspace missing, misaligned or too small    */
   EMAGPIE_E_HIP = -7,         /* a HIP runtime call failed                     */
-  EMAGPIE_E_UNSUPPORTED = -8  /* valid request this build does not provide     */
+  EMAGPIE_E_UNSUPPORTED = -8  /* valid request the library does not provide    */
 } emagpie_status;
 
 /* Execution path of emagpie_epoch (all give bitwise-identical results). */
