@@ -1294,21 +1294,24 @@ __global__ __launch_bounds__((Plan<M, V>::NT)) void k_misfit(const float2* obj, 
   if (tid == 0) phi_all[by_pattern ? k : (int)blockIdx.x] = phi;
 }
 
-// The misfit term of one pattern for the 16 x 8 split at m = 128 (plans 0 and 2)
-// with two workgroups per CU: 512 threads, and half the transformed tile in LDS at a
-// time (S: 128 rows of 64, row stride 65), the other half held in registers.  The
-// rows go in two chunks of 64: the strided row pass loads its exit wave straight
-// from memory (item (row, g) its points g + 16 j), the contiguous row pass leaves
-// each thread one 16-point run per chunk, one in columns 0..63 and one in 64..127
-// (the second chunk's item has the first one's group with bit 2 flipped).  Then
-// the column passes of columns 0..63 in LDS, and those of 64..127 once the other
-// runs are written in.  Every DFT, twiddle product and misfit term is the one the
-// plan's LDS passes compute (misfit_pattern), so the terms are bitwise the same;
-// only the order of the pattern's FP64 sum differs.  The caller has staged the
-// twiddles in tws and synchronised; INT as in misfit_pattern.
+// The misfit term of one pattern at m = 128 (splits 16 x 8 and 8 x 16) with two
+// workgroups per CU: 512 threads, and half the transformed tile in LDS at a time (S:
+// 128 rows of 64, row stride 65), the other half held in registers.  The rows go in two
+// chunks of 64: the strided row pass loads its exit wave straight from memory (item
+// (row, g) its points g + R1 j), the contiguous row pass leaves each thread 16 values of
+// each chunk in registers.  With the 16 x 8 split a thread's contiguous item is one
+// 16-point run, and the second chunk's item has the first one's group with bit 2
+// flipped, so the thread holds one run in columns 0..63 and one in 64..127; with 8 x 16
+// a thread has two 8-point items per chunk, one in each column half.  Then the column
+// passes of columns 0..63 in LDS, and those of 64..127 once the other runs are written
+// in.  Every DFT, twiddle product and misfit term is the one the plan's LDS passes
+// compute (misfit_pattern), so the terms are bitwise the same; only the order of the
+// pattern's FP64 sum differs.  The caller has staged the twiddles in tws and
+// synchronised; INT as in misfit_pattern.
 template <int M, int V>
 struct HalfMisfit {
-  static constexpr bool value = M == 128 && Plan<M, V>::R1 == 16 && Plan<M, V>::R2 == 8;
+  static constexpr int R1 = Plan<M, V>::R1, R2 = Plan<M, V>::R2;
+  static constexpr bool value = M == 128 && ((R1 == 16 && R2 == 8) || (R1 == 8 && R2 == 16));
   static constexpr int NT = 512, H = M / 2;
   static constexpr int LR = M + 1;  // row chunk: 64 rows of 128, stride 129
   static constexpr int LC = H + 1;  // column half: 128 rows of 64, stride 65
@@ -1321,16 +1324,19 @@ __device__ __forceinline__ double misfit_pattern_half(const float2* obj, int n, 
                                                       int2 pk, INT intensity, cx<float>* S,
                                                       const cx<float>* tws, double* redd, int tid) {
   using HM = HalfMisfit<M, V>;
-  constexpr int NTH = HM::NT, H = HM::H, LR = HM::LR, LC = HM::LC;
-  constexpr int R1 = Plan<M, V>::R1, R2 = Plan<M, V>::R2;
-  static_assert(HM::value, "16 x 8 split at m = 128");
-  const int rl = tid % H, gq = tid / H;  // contiguous row item: row rl of the chunk, group gq
-  cx<float> hold[2][R1];
+  constexpr int NTH = HM::NT, H = HM::H, LR = HM::LR, LC = HM::LC, R1 = HM::R1, R2 = HM::R2;
+  static_assert(HM::value, "m = 128, split 16 x 8 or 8 x 16");
+  // items per thread of the strided (R2 points) and contiguous (R1 points) passes over
+  // 64 lines
+  constexpr int IT1 = H * R1 / NTH, IT2 = H * R2 / NTH;
+  static_assert(IT1 * NTH == H * R1 && IT2 * NTH == H * R2 && IT2 * R1 == 16, "items per thread");
+  const int rl = tid % H, gq = tid / H;  // contiguous row items: row rl of the chunk, group gq (+ 8 it)
+  cx<float> hold[2][IT2][R1];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    // strided row pass: 64 rows x 16 groups, two items per thread
+    // strided row pass over the chunk's 64 rows
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < IT1; ++it) {
       const int w = tid + it * NTH;
       const int r = w / R1, g = w % R1;
       const int row = h * H + r;
@@ -1347,40 +1353,54 @@ __device__ __forceinline__ double misfit_pattern_half(const float2* obj, int n, 
       for (int j = 0; j < R2; ++j) S[r * LR + g + R1 * j] = v[j];
     }
     __syncthreads();
-    // contiguous row pass: row rl, group gq (chunk 0) or gq ^ 4 (chunk 1)
-    const int g = gq ^ (h * (R2 / 2));
+    // contiguous row pass: row rl, group gq + 8 it (16 x 8: gq, or gq ^ 4 in chunk 1)
 #pragma unroll
-    for (int j = 0; j < R1; ++j) hold[h][j] = S[rl * LR + R1 * g + j];
-    dft_small<float, false, R1, M>(hold[h], nullptr);
+    for (int it = 0; it < IT2; ++it) {
+      const int g = IT2 == 1 ? (gq ^ (h * (R2 / 2))) : gq + 8 * it;
+#pragma unroll
+      for (int j = 0; j < R1; ++j) hold[h][it][j] = S[rl * LR + R1 * g + j];
+      dft_small<float, false, R1, M>(hold[h][it], nullptr);
+    }
     __syncthreads();
   }
-  // the run in columns 0..63 (A) and the one in 64..127 (B)
+  // 16 x 8: the run in columns 0..63 (A) and the one in 64..127 (B)
   const bool first = gq < R2 / 2;
   const int rowA = first ? rl : H + rl, rowB = first ? H + rl : rl;
   const int cA = R1 * (gq & (R2 / 2 - 1));  // column of the run within its half
   cx<float> hB[R1];
   double acc = 0.0;
-  const int line = tid % H, gl = tid / H;  // contiguous column item: column line, group gl
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
-    if (half == 0) {
+    if constexpr (IT2 == 1) {
+      if (half == 0) {
 #pragma unroll
-      for (int j = 0; j < R1; ++j) {
-        S[rowA * LC + cA + j] = first ? hold[0][j] : hold[1][j];
-        hB[j] = first ? hold[1][j] : hold[0][j];
+        for (int j = 0; j < R1; ++j) {
+          S[rowA * LC + cA + j] = first ? hold[0][0][j] : hold[1][0][j];
+          hB[j] = first ? hold[1][0][j] : hold[0][0][j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < R1; ++j) S[rowB * LC + cA + j] = hB[j];
       }
     } else {
+      // 8 x 16: item it of each chunk lies in column half it (columns 8 gq + j of it)
 #pragma unroll
-      for (int j = 0; j < R1; ++j) S[rowB * LC + cA + j] = hB[j];
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < R1; ++j) S[(h * H + rl) * LC + R1 * gq + j] = hold[h][half][j];
     }
     // this half's intensities, in the order the last pass visits them
-    float dv[R1];
+    float dv[IT2][R1];
 #pragma unroll
-    for (int j = 0; j < R1; ++j) dv[j] = intensity(R1 * gl + j, half * H + line);
+    for (int it = 0; it < IT2; ++it) {
+      const int w = tid + it * NTH, line = w % H, g = w / H;
+#pragma unroll
+      for (int j = 0; j < R1; ++j) dv[it][j] = intensity(R1 * g + j, half * H + line);
+    }
     __syncthreads();
-    // strided column pass over the half's 64 columns, two items per thread
+    // strided column pass over the half's 64 columns
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < IT1; ++it) {
       const int w = tid + it * NTH;
       const int ln = w % H, g = w / H;
       cx<float> v[R2];
@@ -1394,23 +1414,29 @@ __device__ __forceinline__ double misfit_pattern_half(const float2* obj, int n, 
     }
     __syncthreads();
     // contiguous column pass with the misfit terms
-    cx<float> v[R1];
 #pragma unroll
-    for (int j = 0; j < R1; ++j) v[j] = S[(R1 * gl + j) * LC + line];
-    dft_small<float, false, R1, M>(v, nullptr);
+    for (int it = 0; it < IT2; ++it) {
+      const int w = tid + it * NTH, line = w % H, g = w / H;
+      cx<float> v[R1];
 #pragma unroll
-    for (int j = 0; j < R1; ++j) acc += (double)project_px<M>(v[j], dv[j]);
+      for (int j = 0; j < R1; ++j) v[j] = S[(R1 * g + j) * LC + line];
+      dft_small<float, false, R1, M>(v, nullptr);
+#pragma unroll
+      for (int j = 0; j < R1; ++j) acc += (double)project_px<M>(v[j], dv[it][j]);
+    }
     __syncthreads();
   }
   const double tot = block_sum<NTH>(acc, redd, tid);
   return tot / (2.0 * M * M);
 }
 
-// Two workgroups per CU need at most 128 VGPRs (four waves per SIMD): the kernel takes 124
-// as built.  Asking the compiler for four waves per SIMD outright makes it use all 128 and
-// spill, so the bound only states the thread count and a floor of two waves.
+// Two workgroups per CU need at most 128 VGPRs (four waves per SIMD).  The 16 x 8 split
+// takes 125 as built; asking the compiler for four waves per SIMD outright makes it use
+// all 128 and spill, so its bound states only a floor of two waves.  The 8 x 16 split
+// (16-point strided passes) would take 164 unbounded and fits 128 without spilling
+// when asked for four waves.
 template <int M, int V>
-__global__ __launch_bounds__(512, 2) void k_misfit_half(const float2* obj, int n,
+__global__ __launch_bounds__(512, (Plan<M, V>::R2 == 16 ? 4 : 2)) void k_misfit_half(const float2* obj, int n,
                                                         const float2* probe, const float* dperm,
                                                         const int2* pos, const int4* slot,
                                                         const float2* tw, double* phi_all,
