@@ -97,9 +97,9 @@ def test_rectangular_object_gradient():
 
 @pytest.mark.parametrize("plan", [0, 1])
 def test_rectangular_object_misfit_at_m128(plan):
-    """m = 128 on a rectangular object: plan 0 (16 x 8 split) runs the two-workgroups-per-CU
-    misfit kernel, plan 1 the one-tile-per-workgroup kernel; both against the oracle, and the
-    allocation-free misfit bitwise equal to the plan-0 context."""
+    """m = 128 on a rectangular object: the two-workgroups-per-CU misfit kernel of each split
+    (plan 0: 16 x 8, plan 1: 8 x 16) against the oracle, and the allocation-free misfit
+    bitwise equal to the plan-0 context."""
     import paper_2511_01793_amd.emagpie as E
     p = rect_problem(200, 330, m=128, step=(24, 29), photons=1e6, seed=7)
     a = O.amplitudes(p["intensities"])

@@ -89,8 +89,8 @@ def test_c3_minibatch_step_parity_three_levels(c3, path, plan, shape):
     rec.close()
 
 
-# the full misfit over all 10000 patterns: plans 0 and 2 (16 x 8 split) run the
-# two-workgroups-per-CU kernel in the XCD order, plan 1 (8 x 16) the one-tile kernel
+# the full misfit over all 10000 patterns in the XCD order, with the two-workgroups-per-CU
+# kernel of each split: plans 0 and 2 (16 x 8) and plan 1 (8 x 16)
 @pytest.mark.parametrize("plan", [0, 1, 2])
 def test_c3_full_misfit_parity(c3, plan):
     p = c3
