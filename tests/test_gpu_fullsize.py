@@ -1,5 +1,7 @@
-"""Parity at the benchmark's full size (512^2 object, 64^2 probe, 1600 positions, minibatch 64,
-two levels, Poisson 1e6 photons) in the launch configurations the benchmark times."""
+"""Parity at the benchmark workloads' full sizes, in the launch configurations the benchmark
+times: 512^2 object, 64^2 probe, 1600 positions, minibatch 64, two levels (C2); 1024^2 object,
+128^2 probe, 10000 positions, minibatch 256, three levels (C3); 1024^2 object, 256^2 probe, 961
+positions, minibatch 32, two levels (C6)."""
 import numpy as np
 import pytest
 
@@ -101,5 +103,37 @@ def test_c3_full_misfit_parity(c3, plan):
     phi = float(rec.misfit(obj, probe).item())
     torch.cuda.synchronize()
     ref = O.misfit(host(probe), host(obj), p.positions, amps(p))
+    assert abs(phi - ref) <= MISFIT_TOL * ref, (phi, ref)
+    rec.close()
+
+
+@pytest.fixture(scope="module")
+def c6():
+    return problem("c6")
+
+
+# 256^2 patterns at full size (1024^2 object, 961 positions, minibatch 32, two levels): full
+# minibatches of 32 slots (all 16 strips of a slot on one XCD) from a mid-reconstruction
+# state on the fused and graph paths, and the full misfit over all 961 patterns
+@pytest.mark.parametrize("path, shape", [("fused", 8), ("graph", 0)])
+def test_c6_minibatch_step_and_misfit_parity(c6, path, shape):
+    p = c6
+    print("case: c6 step", path, shape, flush=True)
+    rec = make_rec(p, path=path, seed=p.seed, finalize_shape=shape)
+    obj, probe = init_state(p, rec)
+    rec.epoch(obj, probe, 0)
+    a = amps(p)
+    perm = O.permutation(p.seed, 5, p.n_pos)
+    for stage in range(2):
+        idx = perm[stage * 32:(stage + 1) * 32]
+        z0, q0 = host(obj), host(probe)
+        rec.step(obj, probe, idx)
+        torch.cuda.synchronize()
+        q1, z1, _ = O.step_minibatch(q0, z0, p.positions, a, idx, alpha=p.alpha, levels=p.levels)
+        assert rel(host(obj), z1) < STEP_TOL, rel(host(obj), z1)
+        assert rel(host(probe), q1) < STEP_TOL, rel(host(probe), q1)
+    phi = float(rec.misfit(obj, probe).item())
+    torch.cuda.synchronize()
+    ref = O.misfit(host(probe), host(obj), p.positions, a)
     assert abs(phi - ref) <= MISFIT_TOL * ref, (phi, ref)
     rec.close()
