@@ -535,9 +535,11 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
   if constexpr (DG) {
     // The exit wave straight into the first (strided) row pass.  Item i = tid + it NT
     // is row i / R1, group g = i % R1, points g + R1 j: the loads of one j cover
-    // 64 / R1 rows of a wave, R1 consecutive pixels of each.  The pass's twiddles
-    // W^(g j) come from the global table (cache-resident) with the other loads, so
-    // the pass runs before the first barrier.
+    // 64 / R1 rows of a wave, R1 consecutive pixels of each.  The pass runs before the
+    // first barrier: a launch that stages its twiddles here (STAGE) reads the pass's
+    // W^(g j) from the global table (cache-resident) with the other loads; the kernels
+    // that staged them in LDS once at their start (persistent, chain) read them there
+    // and hold fewer registers.
     constexpr int R1 = Plan<M, V>::R1, R2 = Plan<M, V>::R2, DIT = M * R1 / NT;
     static_assert(DIT * NT == M * R1, "direct-gather items per thread");
     cx<float> ps[DIT][R2], twr[DIT][R2];
@@ -551,8 +553,10 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
           q[it][j] = ld(a.probe, (size_t)row * M + g + R1 * j);
           zz[it][j] = ld(zwin, (size_t)row * n + g + R1 * j);
         }
+        if constexpr (STAGE) {
 #pragma unroll
-        for (int j = 1; j < R2; ++j) twr[it][j] = ld(a.tw, g * j);
+          for (int j = 1; j < R2; ++j) twr[it][j] = ld(a.tw, g * j);
+        }
       }
       if constexpr (AS == 0) load_amps();
 #pragma unroll
@@ -571,7 +575,7 @@ __device__ __forceinline__ double patch_step(const StepArgs& a, int s, cx<float>
       const int i = tid + it * NT, row = i / R1, g = i % R1;
       dft_small<float, false, R2, M>(ps[it], tws);
 #pragma unroll
-      for (int j = 1; j < R2; ++j) ps[it][j] = mul_fma(twr[it][j], ps[it][j]);
+      for (int j = 1; j < R2; ++j) ps[it][j] = mul_fma(STAGE ? twr[it][j] : tws[g * j], ps[it][j]);
 #pragma unroll
       for (int j = 0; j < R2; ++j) A[row * LS + g + R1 * j] = ps[it][j];
     }
